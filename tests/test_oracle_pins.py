@@ -1,0 +1,496 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each check uses a closed form,
+an algebraic identity, an exact invariant, a textbook solution, a measured
+convergence order or a symmetry, chosen so that a plausible slip in the
+oracle (a dropped source term, a wrong sign or index, a transposed operand)
+breaks at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import dg2_oracle as O
+from paper_2010_02003_amd import workloads as WL
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+G = 9.81
+
+
+def _prm(nx, ny, dx=1.0, dy=None, **kw):
+    return O.Params(nx=nx, ny=ny, dx=dx, dy=dx if dy is None else dy, **kw)
+
+
+# ---------------------------------------------------------------------------
+# Eq. (2)-(3): modes of planar data are exact
+# ---------------------------------------------------------------------------
+
+def test_modes_of_planar_corner_data_are_exact():
+    nx, ny, dx, dy = 7, 5, 2.0, 0.5
+    X, Y = WL.corner_xy(nx, ny, dx, dy, 10.0, -3.0)
+    a, b, c = 1.25, -0.3, 0.7
+    m = O.modes_from_corners(a + b * X + c * Y)
+    XC, YC = WL.cell_xy(nx, ny, dx, dy, 10.0, -3.0)
+    # Eq. (2): U = U0 + (x-xc)/(dx/2) U1x + (y-yc)/(dy/2) U1y reproduces the plane
+    assert torch.allclose(m[0], torch.tensor(a + b * XC + c * YC), atol=1e-13)
+    assert torch.allclose(m[1], torch.full((ny, nx), b * dx / 2, dtype=torch.float64), atol=1e-14)
+    assert torch.allclose(m[2], torch.full((ny, nx), c * dy / 2, dtype=torch.float64), atol=1e-14)
+
+
+def test_bed_is_continuous_at_faces():
+    Z = np.random.default_rng(0).normal(size=(6, 9))
+    bed = O.bed_from_corners(Z)
+    z0, z1x, z1y = bed.z
+    # east limit of a cell equals the west limit of its east neighbour (Sec. 2.1.2)
+    assert torch.allclose(z0[:, :-1] + z1x[:, :-1], z0[:, 1:] - z1x[:, 1:], atol=1e-14)
+    assert torch.allclose(z0[:-1, :] + z1y[:-1, :], z0[1:, :] - z1y[1:, :], atol=1e-14)
+    assert torch.allclose(bed.zfx[:, 1:], z0 + z1x, atol=1e-14)
+    assert torch.allclose(bed.zfy[1:, :], z0 + z1y, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Numerical flux
+# ---------------------------------------------------------------------------
+
+def _rand_states(n, seed, dry=False):
+    r = np.random.default_rng(seed)
+    h = torch.tensor(r.uniform(0.05, 2.0, n))
+    u = torch.tensor(r.uniform(-3.0, 3.0, n))
+    v = torch.tensor(r.uniform(-1.0, 1.0, n))
+    return h, u, v
+
+
+def test_hll_is_consistent():
+    h, u, v = _rand_states(500, 1)
+    F = O.hll_flux(h, u, v, h, u, v, G, 1e-5)
+    q = h * u
+    exact = torch.stack([q, q * u + 0.5 * G * h * h, q * v])
+    assert torch.allclose(F, exact, rtol=1e-13, atol=1e-13)
+
+
+def test_hll_satisfies_integral_jump_conditions():
+    """F = F_L + s_L (U* - U_L) = F_R + s_R (U* - U_R) with the HLL middle state."""
+    hL, uL, vL = _rand_states(400, 2)
+    hR, uR, vR = _rand_states(400, 3)
+    tol = 1e-5
+    F = O.hll_flux(hL, uL, vL, hR, uR, vR, G, tol)
+    cL, cR = torch.sqrt(G * hL), torch.sqrt(G * hR)
+    # two-rarefaction estimates (Toro) for the middle speeds
+    us = 0.5 * (uL + uR) + cL - cR
+    cs = 0.5 * (cL + cR) + 0.25 * (uL - uR)
+    sL = torch.minimum(uL - cL, us - cs)
+    sR = torch.maximum(uR + cR, us + cs)
+    sub = (sL < 0) & (sR > 0)
+    UL = torch.stack([hL, hL * uL, hL * vL])
+    UR = torch.stack([hR, hR * uR, hR * vR])
+    FL = torch.stack([hL * uL, hL * uL * uL + 0.5 * G * hL * hL, hL * uL * vL])
+    FR = torch.stack([hR * uR, hR * uR * uR + 0.5 * G * hR * hR, hR * uR * vR])
+    Ustar = (sR * UR - sL * UL - (FR - FL)) / (sR - sL)
+    assert torch.allclose(F[:, sub], (FL + sL * (Ustar - UL))[:, sub], rtol=1e-11, atol=1e-11)
+    assert torch.allclose(F[:, sub], (FR + sR * (Ustar - UR))[:, sub], rtol=1e-11, atol=1e-11)
+    # supercritical: the upwind physical flux
+    right = sL >= 0
+    left = sR <= 0
+    assert right.any() or left.any()
+    assert torch.equal(F[:, right], FL[:, right])
+    assert torch.equal(F[:, left], FR[:, left])
+
+
+def test_hll_dry_bed_front_speed_and_wall():
+    # dam break onto a dry bed: s_R is the dry-front speed u_L + 2 c_L (Ritter)
+    hL = torch.tensor([1.0], dtype=torch.float64)
+    z = torch.zeros(1, dtype=torch.float64)
+    F = O.hll_flux(hL, z, z, z, z, z, G, 1e-5)
+    cL = math.sqrt(G)
+    sL, sR = -cL, 2 * cL
+    FL = torch.tensor([0.0, 0.5 * G, 0.0], dtype=torch.float64)
+    UL = torch.tensor([1.0, 0.0, 0.0], dtype=torch.float64)
+    expect = (sR * FL + sL * sR * (torch.zeros(3, dtype=torch.float64) - UL)) / (sR - sL)
+    assert torch.allclose(F[:, 0], expect, rtol=1e-14)
+    # mirror state across a wall: mass flux exactly zero
+    h, u, v = _rand_states(300, 5)
+    F = O.hll_flux(h, u, v, h, -u, v, G, 1e-5)
+    assert torch.equal(F[0], torch.zeros_like(F[0]))
+    # both sides dry: no flux at all
+    hd = torch.tensor([3e-6], dtype=torch.float64)
+    assert torch.equal(O.hll_flux(hd, z, z, hd, z, z, G, 1e-5), torch.zeros(3, 1, dtype=torch.float64))
+
+
+# ---------------------------------------------------------------------------
+# Well-balancedness (Sec. 2.1.2) and conservation
+# ---------------------------------------------------------------------------
+
+def test_lake_at_rest_submerged_bump_stays_still():
+    sc = WL.dambreak_bump(nx=24, ny=20)
+    U = O.initial_state(sc.Z, np.full_like(sc.Z, 1.0), True)
+    bed = O.bed_from_corners(sc.Z)
+    prm = O.params_from_scenario(sc)
+    L = O.spatial_operator(U, bed, prm, 0.0)
+    assert float(L.abs().max()) < 1e-13
+    r = O.run(U, bed, prm, steps=200)
+    assert float(r.U[1:].abs().max()) < 1e-12
+    assert float((r.U[0] - U[0]).abs().max()) < 1e-12
+
+
+def _wall_lake(transpose, variant):
+    """Still water against a high wall and a small step, wet/dry front on a steep cell."""
+    nx, ny = 20, 6
+    X, Y = WL.corner_xy(nx, ny, 1.0, 1.0)
+    Z = np.where(X <= 10, 0.0, 2.0)
+    Z = np.where(X <= 4, 0.3, Z)
+    if transpose:
+        Z = Z.T.copy()
+        nx, ny = ny, nx
+    U = O.initial_state(Z, np.full_like(Z, 1.0), True)
+    bed = O.bed_from_corners(Z)
+    prm = _prm(nx, ny, manning=0.02, variant=variant)
+    # the cell holding the wall is partly wet: zero mean depth, negative face limit
+    h_face = U[0, 0] + (U[0, 2] if transpose else U[0, 1])
+    assert float(h_face.min()) < -0.5
+    return U, O.run(U, bed, prm, steps=300).U
+
+
+@pytest.mark.parametrize("variant", ["NL", "LL"])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_lake_at_rest_against_high_wall_stays_still(transpose, variant):
+    """Sec. 2.1.2: the revised bed z* = z - max(0, -h^-) keeps water blocked by a
+    high wall motionless; without it the wall cell would start to move."""
+    U0, U = _wall_lake(transpose, variant)
+    assert float(U[1:].abs().max()) < 1e-13
+    assert float((U[0] - U0[0]).abs().max()) < 1e-13
+
+
+def test_mass_conserved_with_walls():
+    sc = WL.dambreak_bump(nx=30, ny=22)
+    U, bed, prm = O.setup(sc)
+    m0 = O.mass(U, prm)
+    r = O.run(U, bed, prm, steps=150)
+    assert abs(O.mass(r.U, prm) - m0) <= 1e-13 * m0
+
+
+def test_mass_budget_with_rain_and_inflow():
+    nx, ny, dx = 20, 16, 2.0
+    Z = WL.fbm_surface((ny + 1, nx + 1), 0.7, 1.0, 7)
+    f64 = torch.float64
+    bc = O.InflowBC(O.WEST, 5, 9, torch.tensor([0.0, 10.0, 40.0], dtype=f64),
+                    torch.tensor([0.0, 3.0, 1.0], dtype=f64))
+    bc2 = O.InflowBC(O.NORTH, 2, 4, torch.tensor([0.0, 100.0], dtype=f64),
+                     torch.tensor([0.5, 0.5], dtype=f64))
+    prm = _prm(nx, ny, dx, manning=0.03, inflows=[bc, bc2], rain=(1e-3, 3.0, 20.0))
+    U = O.initial_state(Z, np.zeros_like(Z), False)
+    bed = O.bed_from_corners(Z)
+    r = O.run(U, bed, prm, steps=60)
+    t = 0.0
+    added = 0.0
+    for dt in r.dts:
+        for b in (bc, bc2):
+            added += 0.5 * dt * (float(O.hydrograph_value(b, t)) + float(O.hydrograph_value(b, t + dt)))
+        added += O.rain_depth(prm, t, dt) * nx * ny * dx * dx
+        t += dt
+    assert added > 0
+    assert abs(O.mass(r.U, prm) - added) <= 1e-12 * added
+    assert float(r.U[0, 0].min()) > -1e-12
+
+
+# ---------------------------------------------------------------------------
+# Textbook solution: 1D dam break (Stoker)
+# ---------------------------------------------------------------------------
+
+def _stoker_profile(x, t, x_dam, s):
+    cL = math.sqrt(s["g"] * s["h_L"])
+    xi = (x - x_dam) / t
+    h = np.where(xi < s["head_speed"], s["h_L"], 0.0)
+    fan = (xi >= s["head_speed"]) & (xi < s["tail_speed"])
+    h = np.where(fan, (2 * cL - xi) ** 2 / (9 * s["g"]), h)
+    h = np.where((xi >= s["tail_speed"]) & (xi < s["shock_speed"]), s["h_m"], h)
+    h = np.where(xi >= s["shock_speed"], s["h_R"], h)
+    return h
+
+
+def _stoker_l1(variant, nx):
+    s = json.load(open(os.path.join(GOLDEN, "stoker_dambreak.json")))
+    Lx = 100.0
+    dx = Lx / nx
+    X, _ = WL.corner_xy(nx, 2, dx, dx)
+    Z = np.zeros_like(X)
+    eta = np.where(X < 50.0, s["h_L"], s["h_R"])
+    U = O.initial_state(Z, eta, True)
+    bed = O.bed_from_corners(Z)
+    prm = _prm(nx, 2, dx, cfl=0.3, variant=variant)
+    T = 8.0
+    r = O.run(U, bed, prm, t_end=T)
+    assert r.t == T
+    # exact cell averages by fine midpoint sampling
+    sub = 64
+    xf = (np.arange(nx * sub) + 0.5) * dx / sub
+    exact = _stoker_profile(xf, T, 50.0, s).reshape(nx, sub).mean(axis=1)
+    h = r.U[0, 0].numpy()
+    assert np.abs(h[0] - h[1]).max() < 1e-13  # y-uniform stays y-uniform
+    assert float(r.U[2].abs().max()) < 1e-13  # and qy stays zero
+    return np.abs(h[0] - exact).mean(), h[0], exact
+
+
+@pytest.mark.parametrize("variant", ["NL", "LL"])
+def test_stoker_dam_break(variant):
+    e1, h1, ex = _stoker_l1(variant, 100)
+    e2, _, _ = _stoker_l1(variant, 200)
+    assert e1 < 6e-3
+    assert e2 < 0.75 * e1  # converges under refinement
+    # middle state is reproduced
+    s = json.load(open(os.path.join(GOLDEN, "stoker_dambreak.json")))
+    mid = (np.arange(100) + 0.5) > 50 + (s["tail_speed"] * 8 + 6)
+    mid &= (np.arange(100) + 0.5) < 50 + s["shock_speed"] * 8 - 6
+    assert np.abs(h1[mid] - s["h_m"]).max() < 2e-3
+
+
+def test_local_limiter_removes_shock_undershoot():
+    """Eq. (7) is a TVD minmod: with the detector always on (threshold 0) the
+    undershoot of DG2-NL ahead of the Stoker shock disappears."""
+    s = json.load(open(os.path.join(GOLDEN, "stoker_dambreak.json")))
+    out = {}
+    for variant, theta in (("NL", 10.0), ("LL", 0.0)):
+        nx, dx = 100, 1.0
+        X, _ = WL.corner_xy(nx, 2, dx, dx)
+        Z = np.zeros_like(X)
+        U = O.initial_state(Z, np.where(X < 50.0, 1.0, 0.5), True)
+        prm = _prm(nx, 2, dx, variant=variant, theta=theta)
+        out[variant] = O.run(U, O.bed_from_corners(Z), prm, t_end=8.0).U[0, 0, 0].numpy()
+    assert out["NL"][66:].min() < s["h_R"] - 1e-2
+    assert out["LL"][66:].min() >= s["h_R"] - 1e-12
+    assert out["LL"][60:80].max() < out["NL"][60:80].max()
+
+
+# ---------------------------------------------------------------------------
+# Second-order accuracy (Sec. 2 intro: the slope-decoupled form keeps second order)
+# ---------------------------------------------------------------------------
+
+def _smooth_run(nx):
+    Lx = 100.0
+    dx = Lx / nx
+    X, _ = WL.corner_xy(nx, 1, dx, dx)
+    Z = 0.2 + 0.1 * np.cos(2 * np.pi * X / Lx)
+    eta = 1.0 + 0.05 * np.exp(-((X - 40.0) ** 2) / 60.0)
+    U = O.initial_state(Z, eta, True)
+    bed = O.bed_from_corners(Z)
+    prm = _prm(nx, 1, dx, cfl=0.3)
+    r = O.run(U, bed, prm, t_end=3.0)
+    return r.U[0, 0, 0].numpy()
+
+
+def test_second_order_convergence_smooth_flow():
+    ref_n = 1280
+    ref = _smooth_run(ref_n)
+    errs = []
+    for n in (40, 80, 160):
+        h = _smooth_run(n)
+        coarse_ref = ref.reshape(n, ref_n // n).mean(axis=1)
+        errs.append(np.abs(h - coarse_ref).mean())
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert min(orders) >= 1.8, (errs, orders)
+
+
+# ---------------------------------------------------------------------------
+# Friction (Sec. 2.1.3)
+# ---------------------------------------------------------------------------
+
+def test_friction_point_update():
+    r = np.random.default_rng(4)
+    h = torch.tensor(r.uniform(0.01, 2.0, 200))
+    qx = torch.tensor(r.uniform(-2, 2, 200))
+    qy = torch.tensor(r.uniform(-2, 2, 200))
+    n = 0.04
+    dx_, dy_ = O.friction_increment(h, qx, qy, n, 0.5, G, 1e-5)
+    q0 = torch.sqrt(qx * qx + qy * qy)
+    q1 = torch.sqrt((qx + dx_) ** 2 + (qy + dy_) ** 2)
+    assert bool((q1 <= q0).all())  # friction never accelerates
+    assert bool((torch.sign(qx + dx_) * torch.sign(qx) >= 0).all())  # nor reverses
+    zx, zy = O.friction_increment(h, qx, qy, 0.0, 0.5, G, 1e-5)
+    assert bool((zx == 0).all() and (zy == 0).all())
+    # 1D: error against the exact ODE solution q/(1 + a dt |q|) is O(dt^2)
+    hq, qq = torch.tensor([0.3]), torch.tensor([0.8])
+    a = G * n * n * 0.3 ** (-7.0 / 3.0)
+    errs = []
+    for dt in (0.4, 0.2, 0.1):
+        d, _ = O.friction_increment(hq, qq, torch.zeros(1), n, dt, G, 1e-5)
+        exact = 0.8 / (1 + a * dt * 0.8)
+        errs.append(abs(float(qq + d) - exact))
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
+
+
+def test_friction_planar_modes():
+    rng = np.random.default_rng(3)
+    W = torch.tensor(rng.uniform(0.5, 1.0, (3, 3, 4, 5)))
+    W[0, 1:] *= 0.2
+    out = O.apply_friction(W, 0.0, 1.0, G, 1e-5)
+    assert torch.equal(out, W)  # no friction: identity
+    out = O.apply_friction(W, 0.05, 1.0, G, 1e-5)
+    assert torch.equal(out[0], W[0])  # depth untouched
+    # slope increment is the exact derivative of the Gauss-point values
+    s3 = math.sqrt(3)
+    for var in (1, 2):
+        up = out[var, 0] + out[var, 1] / s3
+        dn = out[var, 0] - out[var, 1] / s3
+        hp = W[0, 0] + W[0, 1] / s3
+        qxp, qyp = W[1, 0] + W[1, 1] / s3, W[2, 0] + W[2, 1] / s3
+        hm = W[0, 0] - W[0, 1] / s3
+        qxm, qym = W[1, 0] - W[1, 1] / s3, W[2, 0] - W[2, 1] / s3
+        ip = O.friction_increment(hp, qxp, qyp, 0.05, 1.0, G, 1e-5)[var - 1]
+        im = O.friction_increment(hm, qxm, qym, 0.05, 1.0, G, 1e-5)[var - 1]
+        base_p = W[var, 0] + W[var, 1] / s3
+        base_m = W[var, 0] - W[var, 1] / s3
+        # point values move by the mean increment plus/minus half the Gauss difference
+        ic = O.friction_increment(W[0, 0], W[1, 0], W[2, 0], 0.05, 1.0, G, 1e-5)[var - 1]
+        assert torch.allclose(up - base_p, ic + 0.5 * (ip - im), atol=1e-14)
+        assert torch.allclose(dn - base_m, ic - 0.5 * (ip - im), atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Local limiting (Eq. 6-7)
+# ---------------------------------------------------------------------------
+
+def _ll_prm(nx, ny, **kw):
+    return _prm(nx, ny, variant="LL", **kw)
+
+
+def test_limiter_leaves_linear_data_alone():
+    nx, ny = 9, 7
+    X, Y = WL.corner_xy(nx, ny, 1.0, 1.0)
+    Z = 0.05 * X - 0.02 * Y
+    W = O.initial_state(Z, 2.0 + 0.1 * X + 0.3 * Y, True, 0.4 * X - 0.1 * Y, 0.2 * Y)
+    bed = O.bed_from_corners(Z)
+    out = O.local_limit(W, bed, _ll_prm(nx, ny))
+    # interior cells have no jumps at their faces: nothing is limited
+    assert torch.allclose(out[:, :, 1:-1, 1:-1], W[:, :, 1:-1, 1:-1], atol=0, rtol=0)
+
+
+def test_limiter_step_hand_case():
+    nx, ny = 5, 1
+    W = torch.zeros(3, 3, ny, nx, dtype=torch.float64)
+    W[0, 0, 0] = torch.tensor([1.0, 1.0, 1.0, 0.4, 0.4], dtype=torch.float64)
+    W[1, 0, 0] = torch.tensor([0.0, 0.1, 0.5, 0.9, 0.9], dtype=torch.float64)
+    W[1, 1, 0, 2] = 0.6  # steep qx slope at the middle cell
+    bed = O.bed_from_corners(np.zeros((ny + 1, nx + 1)))
+    out = O.local_limit(W, bed, _ll_prm(nx, ny))
+    # qx at cell 2: jumps |(0.9-0)-(0.5+0.6)| = 0.2, |(0.5-0.6)-(0.1+0)| = 0.2
+    # scale 0.5 * max(|0.5-0.6/r3|, |0.5+0.6/r3|) = 0.4232 -> 10*0.4232 > 0.2: not limited
+    assert float(out[1, 1, 0, 2]) == 0.6
+    W[1, 1, 0, 2] = 3.0
+    out = O.local_limit(W, bed, _ll_prm(nx, ny))
+    # jumps |0.9-3.5| = 2.6, |-2.5-0.1| = 2.6; scale 0.5*max(|0.5-3/r3|,|0.5+3/r3|)=1.116
+    # 2.6 < 11.16 -> still no limiting; the detector only fires for real shocks
+    assert float(out[1, 1, 0, 2]) == 3.0
+    prm = _ll_prm(nx, ny)
+    prm.theta = 1.0
+    out = O.local_limit(W, bed, prm)
+    # 2.6 > 1.116: minmod(3.0, 0.9-0.5, 0.5-0.1) = 0.4
+    assert abs(float(out[1, 1, 0, 2]) - 0.4) < 1e-15
+    # depth slope goes through the free surface: flat bed -> eta slope = h slope
+    # h = [1, 1, 1, .4, .4] with slope -0.5 in cell 3: jumps 0.5 and 0.1 against
+    # 0.5 * max|0.4 -+ 0.5/r3| = 0.344 -> limited to minmod(-0.5, 0, -0.6) = 0
+    W[0, 1, 0, 3] = -0.5
+    out = O.local_limit(W, bed, prm)
+    assert float(out[0, 1, 0, 3]) == 0.0
+    # a dry neighbour switches limiting off
+    W[0, 0, 0, 1] = 5e-6
+    out = O.local_limit(W, bed, prm)
+    assert float(out[1, 1, 0, 2]) == 3.0
+
+
+def test_limiter_uses_free_surface_not_depth():
+    """A terrain step must not trigger limiting of a lake at rest (Sec. 2.1.3)."""
+    nx, ny = 10, 3
+    X, Y = WL.corner_xy(nx, ny, 1.0, 1.0)
+    Z = np.where(X > 4.5, 0.6, 0.0) + 0.01 * X
+    W = O.initial_state(Z, np.full_like(Z, 1.0), True)
+    bed = O.bed_from_corners(Z)
+    prm = _ll_prm(nx, ny)
+    prm.theta = 0.0  # detector always fires if any jump exists
+    out = O.local_limit(W, bed, prm)
+    assert torch.allclose(out[0, 1] + bed.z[1], torch.zeros_like(out[0, 1]), atol=1e-14)
+
+
+def test_ll_with_infinite_threshold_is_nl():
+    sc = WL.dambreak_bump(nx=20, ny=18, steps=15)
+    U, bed, prm = O.setup(sc)
+    a = O.run(U, bed, prm, steps=15).U
+    prm.variant = "LL"
+    prm.theta = math.inf
+    b = O.run(U, bed, prm, steps=15).U
+    assert torch.equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# Symmetries of Eq. (4)
+# ---------------------------------------------------------------------------
+
+def test_transposed_problem_gives_transposed_result():
+    nx, ny = 14, 11
+    r = np.random.default_rng(8)
+    Z = WL.fbm_surface((ny + 1, nx + 1), 0.7, 0.5, 9)
+    eta = 1.0 + 0.3 * (r.uniform(size=Z.shape) > 0.5)
+    U = O.initial_state(Z, eta, True)
+    bed = O.bed_from_corners(Z)
+    prm = _prm(nx, ny, 1.0, 1.0, manning=0.03)
+    a = O.run(U, bed, prm, steps=25)
+    Ut = O.initial_state(Z.T, eta.T, True)
+    bed_t = O.bed_from_corners(Z.T)
+    prm_t = _prm(ny, nx, 1.0, 1.0, manning=0.03)
+    b = O.run(Ut, bed_t, prm_t, steps=25)
+    # transpose: swap x and y axes, swap qx and qy, swap the 1x and 1y modes
+    bt = b.U.permute(0, 1, 3, 2)[[0, 2, 1]][:, [0, 2, 1]]
+    assert torch.allclose(a.U, bt, atol=1e-12)
+    assert a.dts == pytest.approx(b.dts, rel=1e-13)
+
+
+def test_dam_break_mirror_symmetry():
+    sc = WL.dambreak_bump(nx=32, ny=32, steps=40)
+    sc.Z = sc.Z  # bump centred: the problem is symmetric about the mid-line y = 16
+    U, bed, prm = O.setup(sc)
+    r = O.run(U, bed, prm, steps=40)
+    V = r.U
+    flip = V.flip(-2)
+    sign = torch.tensor([[1, 1, -1], [1, 1, -1], [-1, -1, 1]], dtype=torch.float64).reshape(3, 3, 1, 1)
+    assert torch.allclose(V, flip * sign, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Gauges and diagnostics
+# ---------------------------------------------------------------------------
+
+def test_gauges_sample_the_planar_solution():
+    nx, ny = 6, 4
+    X, Y = WL.corner_xy(nx, ny, 2.0, 2.0)
+    Z = 0.1 * X
+    U = O.initial_state(Z, 1.0 + 0.05 * X - 0.02 * Y + 0.1 * 0.1 * X, True, 0.3 + 0 * X, 0 * X)
+    bed = O.bed_from_corners(Z)
+    prm = _prm(nx, ny, 2.0)
+    pts = np.array([[3.3, 5.1], [11.9, 0.2]])
+    s = O.sample_gauges(U, bed, prm, pts)
+    for k, (x, y) in enumerate(pts):
+        eta = 1.0 + 0.05 * x - 0.02 * y + 0.01 * x
+        assert abs(float(s[k, 1]) - eta) < 1e-13
+        assert abs(float(s[k, 0]) - (eta - 0.1 * x)) < 1e-13
+        assert abs(float(s[k, 2]) - 0.3 / float(s[k, 0])) < 1e-12
+
+
+def test_energy_of_lake_at_rest_is_closed_form():
+    nx, ny, dx = 5, 4, 2.0
+    Z = np.zeros((ny + 1, nx + 1))
+    U = O.initial_state(Z, np.full_like(Z, 1.5), True)
+    bed = O.bed_from_corners(Z)
+    prm = _prm(nx, ny, dx)
+    # Eq. (12): E = integral of g/2 (eta^2 - z^2) = g/2 * 1.5^2 * area
+    assert abs(O.energy(U, bed, prm) - 0.5 * G * 2.25 * nx * ny * dx * dx) < 1e-10
+
+
+def test_paper_constants_fixture():
+    c = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
+    prm = O.Params(nx=1, ny=1, dx=1.0, dy=1.0)
+    assert prm.cfl == c["courant_number_dg2"]["value"]
+    assert prm.tol == c["tol_dry"]["value"]
+    assert prm.theta == c["shock_detector_threshold"]["value"]
+    assert abs(1.0 / O.SQRT3 - c["gauss_point_offset"]["value"]) < 1e-16
