@@ -1,0 +1,215 @@
+/*
+ * dg2.h - C ABI of the MI355X (gfx950) DG2 flood-model time step.
+ *
+ * The library advances the 2D shallow water equations with the
+ * slope-decoupled second-order discontinuous Galerkin (DG2) method of
+ * Ayog, Kesserwani, Shaw, Sharifian & Bau, "Second-order discontinuous
+ * Galerkin flood model: comparison with industry-standard finite volume
+ * models", Sec. 2.1, on one GPU:
+ *
+ *   - per-element planar modes (mean, x-slope, y-slope) of h, hu, hv
+ *     (Sec. 2.1.1, Eq. 2) on a uniform grid of nx x ny rectangles (Sec. 2);
+ *   - face limits, positivity-preserving dummy limits and the wall revision
+ *     of the bed, an HLL two-argument flux, dummy modes and the operators
+ *     L0, L1x, L1y with the well-balanced bed source (Sec. 2.1.2, Eq. 4-5);
+ *   - implicit Manning friction split at the centre and the four Gauss
+ *     points before each RK2 step (Sec. 2.1.3, Eq. 1 for C_f);
+ *   - optional local slope limiting, DG2-LL (Sec. 2.1.3, Eq. 6-7);
+ *   - explicit two-stage RK2 with a Courant-limited global time step
+ *     (Sec. 2.1.2).
+ *
+ * Conventions shared by every call:
+ *   - Cells are indexed c = j*nx + i, i west->east, j south->north; the cell
+ *     centre is (x0 + (i+0.5) dx, y0 + (j+0.5) dy).
+ *   - Corner arrays hold (ny+1)*(nx+1) values, row-major, x fastest.
+ *   - A mode state is 9 planes of nx*ny values in the order
+ *       h0, h1x, h1y, qx0, qx1x, qx1y, qy0, qy1x, qy1y
+ *     (mean and slope coefficients of Eq. 2 for h, hu, hv).
+ *   - Host arrays are always double and are copied during the call; the
+ *     caller keeps ownership.  FP32 contexts convert on the way in and out.
+ *   - Every call returns a dg2_status and never aborts or throws.  The text
+ *     of the last failure on a context is returned by dg2_last_error(ctx);
+ *     dg2_last_error(NULL) gives the last failure of dg2_create on this
+ *     thread.  Invalid sizes or parameters, NaN inputs and negative depths,
+ *     discharges or Manning values return DG2_EINVAL and change nothing.
+ *   - Numerical failures found on the device (NaN, a mean depth below
+ *     -1e-6 m) are latched and returned as DG2_ENUMERIC by the next
+ *     dg2_sync, dg2_get_state, dg2_read_gauges or dg2_diagnostics.
+ *   - Work is queued on the context's HIP stream; calls that return host
+ *     data synchronise that stream.  A context must be used from one host
+ *     thread at a time.
+ */
+#ifndef DG2_H
+#define DG2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg2_ctx dg2_ctx;
+
+typedef enum {
+  DG2_OK = 0,
+  DG2_EINVAL = -1,       /* bad argument; nothing was changed            */
+  DG2_ENOMEM = -2,       /* device or host allocation failed             */
+  DG2_EHIP = -3,         /* a HIP runtime call failed                    */
+  DG2_ESTATE = -4,       /* call not valid in the current state          */
+  DG2_ENUMERIC = -5,     /* NaN or negative mean depth found on device   */
+  DG2_EUNSUPPORTED = -6  /* option not available in this build           */
+} dg2_status;
+
+typedef enum { DG2_FP64 = 0, DG2_FP32 = 1 } dg2_prec;
+/* DG2_NL: no limiting.  DG2_LL: local limiting of Sec. 2.1.3 (the paper's
+ * DG2-LL, also called DG2+minmod). */
+typedef enum { DG2_NL = 0, DG2_LL = 1 } dg2_variant;
+typedef enum { DG2_WEST = 0, DG2_EAST = 1, DG2_SOUTH = 2, DG2_NORTH = 3 } dg2_side;
+/* Boundary segments default to solid walls (mirror ghost cells).  An inflow
+ * segment takes a discharge hydrograph (dg2_set_inflow_hydrograph). */
+typedef enum { DG2_BC_WALL = 0, DG2_BC_INFLOW_Q = 1 } dg2_bc;
+
+typedef struct {
+  int32_t nx, ny;         /* cells in x and y, each >= 1                      */
+  double dx, dy;          /* element size (m), > 0                            */
+  double x0, y0;          /* south-west corner of the domain (m)              */
+  int32_t prec;           /* dg2_prec: arithmetic and storage of the state    */
+  int32_t variant;        /* dg2_variant                                      */
+  double g;               /* gravity (m/s^2), default 9.81                    */
+  double cfl;             /* Courant number, default 0.3 (Sec. 2.1.2)         */
+  double tol_dry;         /* drying tolerance (m), default 1e-5 (Sec. 2.1.3)  */
+  double ll_threshold;    /* shock-detector threshold, default 10 (Eq. 6)     */
+  double dt_max;          /* cap on the time step (s), default 1              */
+  void *hip_stream;       /* borrowed hipStream_t; NULL: the library makes one */
+} dg2_config;
+
+/* Fill *cfg with the defaults above for an nx x ny grid of dx x dy cells
+ * (FP64, DG2-NL, origin 0, library-owned stream). */
+void dg2_config_default(dg2_config *cfg, int32_t nx, int32_t ny, double dx, double dy);
+
+/* Create a context on the current HIP device.  The grid is flat (z = 0),
+ * dry, frictionless and closed by walls until the setters below change it.
+ * On failure *out is NULL.  Returns DG2_EINVAL, DG2_ENOMEM or DG2_EHIP. */
+dg2_status dg2_create(const dg2_config *cfg, dg2_ctx **out);
+
+/* Release every device and host resource the context allocated.  NULL-safe. */
+void dg2_destroy(dg2_ctx *ctx);
+
+/* Message of the last failing call on ctx (NULL: last dg2_create failure of
+ * this thread).  Valid until the next call on ctx. */
+const char *dg2_last_error(const dg2_ctx *ctx);
+
+/* Bed elevation at the (ny+1)*(nx+1) corner nodes (DEM points, Sec. 2.1.1).
+ * The bed modes z0, z1x, z1y follow Eq. (3) from face-centre averages of the
+ * corners, which makes the bed continuous across faces. */
+dg2_status dg2_set_dem_corners(dg2_ctx *ctx, const double *z);
+
+/* Manning coefficient n_M of Eq. (1): per cell (nx*ny values, >= 0) when
+ * n_cell is not NULL, otherwise the uniform value n_uniform (>= 0). */
+dg2_status dg2_set_manning(dg2_ctx *ctx, const double *n_cell, double n_uniform);
+
+/* Initial condition from corner-node values (Eq. 3): the free surface
+ * eta (is_eta != 0) or the depth h (is_eta == 0), and the unit discharges
+ * qx, qy (NULL = 0).  From eta, the depth modes are the eta modes minus the
+ * bed modes (a discrete lake at rest where eta is flat) and elements with a
+ * negative mean depth are set dry.  Uses the current DEM.  Resets t to 0,
+ * the step counter and the gauge record, and computes the first time step. */
+dg2_status dg2_set_initial_corners(dg2_ctx *ctx, const double *surface, int32_t is_eta,
+                                   const double *qx, const double *qy);
+
+/* Replace the state by 9*nx*ny mode values (plane order above) at time t.
+ * Depth modes may make face limits negative; mean depths must be >= 0. */
+dg2_status dg2_set_state(dg2_ctx *ctx, const double *modes9, double t);
+
+/* Copy the state out (modes9: 9*nx*ny doubles, may be NULL) with its time,
+ * completed step count and the last step size (each pointer may be NULL).
+ * Synchronises the stream; returns a latched DG2_ENUMERIC after copying. */
+dg2_status dg2_get_state(dg2_ctx *ctx, double *modes9, double *t, int64_t *step, double *last_dt);
+
+/* Declare cells first..last (0-based along the side: rows for west/east,
+ * columns for south/north) of one side as a wall or an inflow segment.  One
+ * inflow segment per side; DG2_BC_WALL on a side removes its segment.  An
+ * inflow face carries the prescribed flux [q, q^2/h_b + g h_b^2/2, 0] in the
+ * normal direction with q = Q(t)/(segment length) and h_b the larger of the
+ * inner dummy depth and the critical depth of q; Q = 0 leaves a wall. */
+dg2_status dg2_set_boundary(dg2_ctx *ctx, int32_t side, int32_t bc, int32_t first, int32_t last);
+
+/* Discharge hydrograph Q(t) (m^3/s, >= 0) for the side's inflow segment:
+ * n >= 1 samples at increasing times t; linear in between, held constant
+ * outside.  Each RK stage uses Q at its own stage time. */
+dg2_status dg2_set_inflow_hydrograph(dg2_ctx *ctx, int32_t side, const double *t, const double *Q,
+                                     int32_t n);
+
+/* Uniform rainfall of rate (m/s, >= 0) during [t_begin, t_end]: the mean
+ * depth of every element gains rate * |[t, t+dt] intersect [t_begin, t_end]|
+ * at the start of each step.  rate = 0 switches it off. */
+dg2_status dg2_set_rainfall(dg2_ctx *ctx, double rate, double t_begin, double t_end);
+
+/* Gauges at n points (xy: n pairs x, y in m, inside the domain; n <= 64).
+ * After each step the planar solution (Eq. 2) is sampled there as
+ * h, eta = h + z, u, v into a device record that keeps up to capacity
+ * samples (capacity <= 0: 65536).  Clears the record.  n = 0 removes them. */
+dg2_status dg2_set_gauges(dg2_ctx *ctx, const double *xy, int32_t n, int32_t capacity);
+
+/* dt > 0: every step uses this step size (still capped by a run-to target).
+ * dt <= 0: Courant-limited steps, dt = min(Cr min_c m_c, dt_max) with
+ * m_c = min(dx/(|u|+c), dy/(|v|+c)) over wet cell means. */
+dg2_status dg2_set_fixed_dt(dg2_ctx *ctx, double dt);
+
+/* Queue nsteps time steps (asynchronous). */
+dg2_status dg2_step(dg2_ctx *ctx, int32_t nsteps);
+
+/* Advance until t == T: steps are queued in chunks, the last one shortened to
+ * land exactly on T; returns when the stream reaches T.  T <= t is a no-op.
+ * Later dg2_step calls are no longer bounded by T. */
+dg2_status dg2_run_to(dg2_ctx *ctx, double T);
+
+/* Wait for the queued work; returns DG2_ENUMERIC if a failure was latched. */
+dg2_status dg2_sync(dg2_ctx *ctx);
+
+/* Copy the gauge samples recorded since the last read (oldest first) into
+ * out[ns][ng][4] (h, eta, u, v) and t[ns], with ns <= max_samples returned
+ * in *ns; unread samples beyond max_samples stay queued.  If more than the
+ * capacity were recorded since the last read the oldest are lost and the
+ * call returns DG2_ESTATE after copying the rest. */
+dg2_status dg2_read_gauges(dg2_ctx *ctx, double *out, double *t, int32_t max_samples,
+                           int32_t *ns);
+
+/* Domain integrals of the current state, reduced on the device in a fixed
+ * order: mass = sum of h0 dx dy (Eq. 11), energy (Eq. 12, 2x2 Gauss rule per
+ * element) and the smallest mean depth.  Any pointer may be NULL. */
+dg2_status dg2_diagnostics(dg2_ctx *ctx, double *mass, double *energy, double *min_h);
+
+/* Time nsteps steps with HIP events on the context's stream, one event pair
+ * per kernel: average milliseconds of the stage-1 kernel, the stage-2 kernel
+ * and of a whole step (any pointer may be NULL).  The steps are real steps
+ * of the simulation. */
+dg2_status dg2_time_kernels(dg2_ctx *ctx, int32_t nsteps, double *ms_stage1, double *ms_stage2,
+                            double *ms_step);
+
+/* Launch shape of the stage kernels: rows marched per wavefront (>= 1) and
+ * wavefronts per workgroup (1, 2 or 4).  rows <= 0 restores the built-in
+ * choice for this grid.  Results do not depend on it. */
+dg2_status dg2_set_launch(dg2_ctx *ctx, int32_t rows_per_wave, int32_t waves_per_block);
+
+/* Pick the launch shape by timing candidates on copies of the current state
+ * (the state is restored afterwards); budget_ms bounds the time spent.  The
+ * chosen rows-per-wave is returned in *rows (may be NULL). */
+dg2_status dg2_autotune(dg2_ctx *ctx, double budget_ms, int32_t *rows);
+
+/* Bytes of device memory a state needs (9 planes, padded plane stride) and
+ * the plane stride in elements; for dg2_bind_device_state. */
+dg2_status dg2_state_layout(const dg2_ctx *ctx, size_t *bytes, size_t *plane_stride);
+
+/* Keep the state in caller-owned device memory (e.g. a torch tensor) of at
+ * least dg2_state_layout bytes, 256-byte aligned.  The current state is
+ * copied in; the buffer is borrowed and must outlive the context or the
+ * next dg2_bind_device_state(ctx, NULL, 0), which returns to own memory. */
+dg2_status dg2_bind_device_state(dg2_ctx *ctx, void *dev_ptr, size_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG2_H */

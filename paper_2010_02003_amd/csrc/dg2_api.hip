@@ -1,0 +1,811 @@
+// C-ABI runtime of the DG2 library: context, device buffers, problem setup,
+// step queueing, run-to-time, gauges, diagnostics and timing.
+//
+// The host side only moves data and queues kernels; every arithmetic step
+// of the time integration runs in the HIP kernels of dg2_kernels.hip.  The
+// one-off setup arithmetic (bed and initial modes from corner values, Eq. 3)
+// is done here in double precision before upload.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/dg2.h"
+#include "dg2_internal.h"
+
+using namespace dg2;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr int kMaxGauges = 64;
+constexpr int kDiagBlocks = 1024;
+
+}  // namespace
+
+struct dg2_ctx {
+  dg2_config cfg{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int f32 = 0;
+  size_t esz = 8;
+  long long P = 0;  // plane stride (elements)
+  long long ncell = 0;
+  void *U = nullptr, *U1 = nullptr, *W1 = nullptr, *z = nullptr, *n = nullptr;
+  void *U_own = nullptr;
+  bool has_ncell = false;
+  double n_uniform = 0.0;
+  Ctrl *ctrl = nullptr;
+  Ctrl *hctrl = nullptr;  // pinned mirror
+  // host copies used by setup
+  std::vector<double> zc;  // corners
+  std::vector<double> z0, z1x, z1y;
+  // boundaries and hydrographs
+  int seg_first[4] = {1, 1, 1, 1}, seg_last[4] = {0, 0, 0, 0};
+  bool inflow[4] = {false, false, false, false};
+  double *hyd_t[4] = {nullptr, nullptr, nullptr, nullptr};
+  double *hyd_Q[4] = {nullptr, nullptr, nullptr, nullptr};
+  int nhyd[4] = {0, 0, 0, 0};
+  double rain_rate = 0.0, rain_tb = 0.0, rain_te = 0.0;
+  double fixed_dt = 0.0;
+  // gauges
+  int ng = 0, gcap = 0;
+  int *g_cell = nullptr;
+  void *g_xi = nullptr, *g_zeta = nullptr, *g_z = nullptr, *g_buf = nullptr;
+  double *g_t = nullptr;
+  long long g_read = 0;
+  // diagnostics scratch
+  double *diag_part = nullptr, *diag_out = nullptr;
+  // launch shape
+  int R_user = 0, wpb_user = 4;
+  std::string err;
+};
+
+namespace {
+
+dg2_status fail(dg2_ctx *c, dg2_status s, const std::string &msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_create_error = msg;
+  return s;
+}
+
+dg2_status hipfail(dg2_ctx *c, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(c, e == hipErrorOutOfMemory ? DG2_ENOMEM : DG2_EHIP, m);
+}
+
+#define HIPCHK(ctx, expr, what)                  \
+  do {                                           \
+    hipError_t _e = (expr);                      \
+    if (_e != hipSuccess) return hipfail(ctx, _e, what); \
+  } while (0)
+
+bool finite_all(const double *a, size_t n) {
+  for (size_t k = 0; k < n; ++k)
+    if (!std::isfinite(a[k])) return false;
+  return true;
+}
+
+// Eq. (3) from corner values: face-centre averages, then mean and slopes.
+void corner_modes(const double *C, int nx, int ny, double *m0, double *m1x, double *m1y) {
+  const int w = nx + 1;
+  for (int j = 0; j < ny; ++j) {
+    for (int i = 0; i < nx; ++i) {
+      const double E = 0.5 * (C[j * w + i + 1] + C[(j + 1) * w + i + 1]);
+      const double W = 0.5 * (C[j * w + i] + C[(j + 1) * w + i]);
+      const double N = 0.5 * (C[(j + 1) * w + i] + C[(j + 1) * w + i + 1]);
+      const double S = 0.5 * (C[j * w + i] + C[j * w + i + 1]);
+      const size_t c = (size_t)j * nx + i;
+      m0[c] = 0.5 * (E + W);
+      m1x[c] = 0.5 * (E - W);
+      m1y[c] = 0.5 * (N - S);
+    }
+  }
+}
+
+// Copy n doubles from host into a device array of the context precision.
+dg2_status upload(dg2_ctx *c, void *dst, const double *src, size_t n) {
+  if (!c->f32) {
+    HIPCHK(c, hipMemcpyAsync(dst, src, n * 8, hipMemcpyHostToDevice, c->stream), "upload");
+  } else {
+    std::vector<float> tmp(n);
+    for (size_t k = 0; k < n; ++k) tmp[k] = (float)src[k];
+    HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), n * 4, hipMemcpyHostToDevice, c->stream), "upload");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "upload sync");
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream), "upload sync");
+  return DG2_OK;
+}
+
+dg2_status download(dg2_ctx *c, double *dst, const void *src, size_t n) {
+  if (!c->f32) {
+    HIPCHK(c, hipMemcpyAsync(dst, src, n * 8, hipMemcpyDeviceToHost, c->stream), "download");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "download sync");
+  } else {
+    std::vector<float> tmp(n);
+    HIPCHK(c, hipMemcpyAsync(tmp.data(), src, n * 4, hipMemcpyDeviceToHost, c->stream), "download");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "download sync");
+    for (size_t k = 0; k < n; ++k) dst[k] = tmp[k];
+  }
+  return DG2_OK;
+}
+
+char *plane(void *base, const dg2_ctx *c, int k) { return (char *)base + (size_t)k * c->P * c->esz; }
+
+PlanArgs plan_args(const dg2_ctx *c) {
+  PlanArgs p{};
+  p.cfl = c->cfg.cfl;
+  p.dt_max = c->cfg.dt_max;
+  p.fixed_dt = c->fixed_dt;
+  p.rain_rate = c->rain_rate;
+  p.rain_tb = c->rain_tb;
+  p.rain_te = c->rain_te;
+  for (int s = 0; s < 4; ++s) {
+    const bool on = c->inflow[s] && c->nhyd[s] > 0;
+    p.nhyd[s] = on ? c->nhyd[s] : 0;
+    p.hyd_t[s] = c->hyd_t[s];
+    p.hyd_Q[s] = c->hyd_Q[s];
+    const double d = (s == DG2_WEST || s == DG2_EAST) ? c->cfg.dy : c->cfg.dx;
+    p.seg_len[s] = on ? (c->seg_last[s] - c->seg_first[s] + 1) * d : 1.0;
+  }
+  p.ng = c->ng;
+  p.gauge_cap = c->gcap > 0 ? c->gcap : 1;
+  p.gauge_t = c->g_t;
+  return p;
+}
+
+template <typename real>
+Scen<real> scen(const dg2_ctx *c) {
+  Scen<real> s{};
+  s.U = (const real *)c->U;
+  s.U1 = (real *)c->U1;
+  s.W1 = (real *)c->W1;
+  s.z = (const real *)c->z;
+  s.n = c->has_ncell ? (const real *)c->n : nullptr;
+  s.n_uniform = (real)c->n_uniform;
+  s.ctrl = c->ctrl;
+  s.nx = c->cfg.nx;
+  s.ny = c->cfg.ny;
+  s.P = c->P;
+  s.dx = (real)c->cfg.dx;
+  s.dy = (real)c->cfg.dy;
+  s.idx = (real)(1.0 / c->cfg.dx);
+  s.idy = (real)(1.0 / c->cfg.dy);
+  for (int k = 0; k < 4; ++k) {
+    const bool on = c->inflow[k] && c->nhyd[k] > 0;
+    s.seg_first[k] = on ? c->seg_first[k] : 1;
+    s.seg_last[k] = on ? c->seg_last[k] : 0;
+  }
+  s.ng = c->ng;
+  s.g_cell = c->g_cell;
+  s.g_xi = (const real *)c->g_xi;
+  s.g_zeta = (const real *)c->g_zeta;
+  s.g_z = (const real *)c->g_z;
+  s.g_buf = (real *)c->g_buf;
+  s.g_cap = c->gcap > 0 ? c->gcap : 1;
+  return s;
+}
+
+Consts consts(const dg2_ctx *c) {
+  Consts k;
+  k.g = c->cfg.g;
+  k.tol = c->cfg.tol_dry;
+  k.theta = c->cfg.ll_threshold;
+  return k;
+}
+
+Launch launch_of(const dg2_ctx *c) {
+  return make_launch(c->cfg.nx, c->cfg.ny, c->cfg.variant, c->R_user, c->wpb_user);
+}
+
+hipError_t queue_stage(dg2_ctx *c, int stage) {
+  const Launch L = launch_of(c);
+  if (c->f32) return launch_stage<float>(stage, c->cfg.variant, scen<float>(c), consts(c), L, c->stream);
+  return launch_stage<double>(stage, c->cfg.variant, scen<double>(c), consts(c), L, c->stream);
+}
+
+hipError_t queue_plan(dg2_ctx *c, int mode, double t_end = 0.0, int set_tend = 0) {
+  return launch_plan(c->ctrl, plan_args(c), mode, t_end, set_tend, c->stream);
+}
+
+dg2_status queue_step(dg2_ctx *c, hipEvent_t *ev = nullptr) {
+  if (ev) HIPCHK(c, hipEventRecord(ev[0], c->stream), "event");
+  HIPCHK(c, queue_stage(c, 1), "stage 1 launch");
+  if (ev) HIPCHK(c, hipEventRecord(ev[1], c->stream), "event");
+  HIPCHK(c, queue_stage(c, 2), "stage 2 launch");
+  if (ev) HIPCHK(c, hipEventRecord(ev[2], c->stream), "event");
+  HIPCHK(c, queue_plan(c, kPlanFinishStep), "plan launch");
+  return DG2_OK;
+}
+
+// Courant minimum of the state just uploaded, then plan the first step.
+dg2_status prime(dg2_ctx *c) {
+  const unsigned long long inf = kInfBits;
+  HIPCHK(c, hipMemcpyAsync(&c->ctrl->minbits, &inf, 8, hipMemcpyHostToDevice, c->stream), "prime");
+  hipError_t e = c->f32 ? launch_cfl<float>(scen<float>(c), consts(c), c->stream)
+                        : launch_cfl<double>(scen<double>(c), consts(c), c->stream);
+  HIPCHK(c, e, "cfl launch");
+  HIPCHK(c, queue_plan(c, kPlanFromMin), "plan launch");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "prime sync");
+  return DG2_OK;
+}
+
+dg2_status read_ctrl(dg2_ctx *c) {
+  HIPCHK(c, hipMemcpyAsync(c->hctrl, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream),
+         "ctrl read");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "ctrl sync");
+  return DG2_OK;
+}
+
+dg2_status latched(dg2_ctx *c) {
+  if (c->hctrl->flags) {
+    return fail(c, DG2_ENUMERIC,
+                (c->hctrl->flags & kFlagNaN) ? "NaN in the state" : "negative mean depth below -1e-6 m");
+  }
+  return DG2_OK;
+}
+
+dg2_status alloc(dg2_ctx *c, void **p, size_t bytes, const char *what) {
+  HIPCHK(c, hipMalloc(p, bytes), what);
+  HIPCHK(c, hipMemsetAsync(*p, 0, bytes, c->stream), what);
+  return DG2_OK;
+}
+
+dg2_status reset_time(dg2_ctx *c, double t) {
+  Ctrl h{};
+  h.t = t;
+  h.dt = 0.0;
+  h.t_end = std::numeric_limits<double>::infinity();
+  h.cflmin = std::numeric_limits<double>::infinity();
+  h.minbits = kInfBits;
+  h.step = 0;
+  h.gauge_written = 0;
+  *c->hctrl = h;
+  HIPCHK(c, hipMemcpyAsync(c->ctrl, c->hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, c->stream), "ctrl");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "ctrl");
+  c->g_read = 0;
+  return DG2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dg2_config_default(dg2_config *cfg, int32_t nx, int32_t ny, double dx, double dy) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->nx = nx;
+  cfg->ny = ny;
+  cfg->dx = dx;
+  cfg->dy = dy;
+  cfg->prec = DG2_FP64;
+  cfg->variant = DG2_NL;
+  cfg->g = 9.81;
+  cfg->cfl = 0.3;
+  cfg->tol_dry = 1e-5;
+  cfg->ll_threshold = 10.0;
+  cfg->dt_max = 1.0;
+}
+
+const char *dg2_last_error(const dg2_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+void dg2_destroy(dg2_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  void *bufs[] = {c->U_own, c->U1, c->W1, c->z, c->n, c->ctrl, c->g_cell, c->g_xi,
+                  c->g_zeta, c->g_z, c->g_buf, c->g_t, c->diag_part, c->diag_out};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  for (int s = 0; s < 4; ++s) {
+    if (c->hyd_t[s]) (void)hipFree(c->hyd_t[s]);
+    if (c->hyd_Q[s]) (void)hipFree(c->hyd_Q[s]);
+  }
+  if (c->hctrl) (void)hipHostFree(c->hctrl);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+dg2_status dg2_create(const dg2_config *cfg, dg2_ctx **out) {
+  if (!out) return fail(nullptr, DG2_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return fail(nullptr, DG2_EINVAL, "cfg is NULL");
+  if (cfg->nx < 1 || cfg->ny < 1) return fail(nullptr, DG2_EINVAL, "nx and ny must be >= 1");
+  if ((long long)cfg->nx * cfg->ny > (1ll << 30)) return fail(nullptr, DG2_EINVAL, "grid too large");
+  if (!(cfg->dx > 0) || !(cfg->dy > 0) || !std::isfinite(cfg->dx) || !std::isfinite(cfg->dy))
+    return fail(nullptr, DG2_EINVAL, "dx and dy must be positive");
+  if (!(cfg->g > 0) || !(cfg->cfl > 0) || !(cfg->tol_dry > 0) || !(cfg->dt_max > 0) ||
+      !(cfg->ll_threshold >= 0) || !std::isfinite(cfg->x0) || !std::isfinite(cfg->y0))
+    return fail(nullptr, DG2_EINVAL, "g, cfl, tol_dry, dt_max must be > 0 and ll_threshold >= 0");
+  if (cfg->prec != DG2_FP64 && cfg->prec != DG2_FP32) return fail(nullptr, DG2_EINVAL, "bad prec");
+  if (cfg->variant != DG2_NL && cfg->variant != DG2_LL) return fail(nullptr, DG2_EINVAL, "bad variant");
+  if (cfg->variant == DG2_LL) return fail(nullptr, DG2_EUNSUPPORTED, "DG2-LL is not built yet");
+
+  dg2_ctx *c = new (std::nothrow) dg2_ctx();
+  if (!c) return fail(nullptr, DG2_ENOMEM, "host allocation failed");
+  c->cfg = *cfg;
+  c->f32 = cfg->prec == DG2_FP32;
+  c->esz = c->f32 ? 4 : 8;
+  c->ncell = (long long)cfg->nx * cfg->ny;
+  c->P = (c->ncell + 63) / 64 * 64;
+  auto bail = [&](dg2_status s) {
+    g_create_error = c->err;
+    dg2_destroy(c);
+    return s;
+  };
+  hipError_t e;
+  if (cfg->hip_stream) {
+    c->stream = (hipStream_t)cfg->hip_stream;
+  } else {
+    e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(hipfail(c, e, "stream create"));
+    c->own_stream = true;
+  }
+  const size_t pb = (size_t)c->P * c->esz;
+  dg2_status s;
+  if ((s = alloc(c, &c->U_own, 9 * pb, "state")) != DG2_OK) return bail(s);
+  c->U = c->U_own;
+  if ((s = alloc(c, &c->U1, 9 * pb, "stage buffer")) != DG2_OK) return bail(s);
+  if ((s = alloc(c, &c->z, 3 * pb, "bed")) != DG2_OK) return bail(s);
+  if ((s = alloc(c, (void **)&c->ctrl, sizeof(Ctrl), "ctrl")) != DG2_OK) return bail(s);
+  if ((s = alloc(c, (void **)&c->diag_part, kDiagBlocks * 4 * sizeof(double), "diag")) != DG2_OK)
+    return bail(s);
+  if ((s = alloc(c, (void **)&c->diag_out, 4 * sizeof(double), "diag")) != DG2_OK) return bail(s);
+  e = hipHostMalloc((void **)&c->hctrl, sizeof(Ctrl), hipHostMallocDefault);
+  if (e != hipSuccess) return bail(hipfail(c, e, "pinned ctrl"));
+  c->zc.assign((size_t)(cfg->nx + 1) * (cfg->ny + 1), 0.0);
+  c->z0.assign(c->ncell, 0.0);
+  c->z1x.assign(c->ncell, 0.0);
+  c->z1y.assign(c->ncell, 0.0);
+  if ((s = reset_time(c, 0.0)) != DG2_OK) return bail(s);
+  if ((s = prime(c)) != DG2_OK) return bail(s);
+  *out = c;
+  return DG2_OK;
+}
+
+dg2_status dg2_set_dem_corners(dg2_ctx *c, const double *z) {
+  if (!c) return DG2_EINVAL;
+  if (!z) return fail(c, DG2_EINVAL, "z is NULL");
+  const size_t nc = (size_t)(c->cfg.nx + 1) * (c->cfg.ny + 1);
+  if (!finite_all(z, nc)) return fail(c, DG2_EINVAL, "DEM has non-finite values");
+  c->zc.assign(z, z + nc);
+  corner_modes(z, c->cfg.nx, c->cfg.ny, c->z0.data(), c->z1x.data(), c->z1y.data());
+  dg2_status s;
+  if ((s = upload(c, plane(c->z, c, 0), c->z0.data(), c->ncell)) != DG2_OK) return s;
+  if ((s = upload(c, plane(c->z, c, 1), c->z1x.data(), c->ncell)) != DG2_OK) return s;
+  if ((s = upload(c, plane(c->z, c, 2), c->z1y.data(), c->ncell)) != DG2_OK) return s;
+  return DG2_OK;
+}
+
+dg2_status dg2_set_manning(dg2_ctx *c, const double *n_cell, double n_uniform) {
+  if (!c) return DG2_EINVAL;
+  if (n_cell) {
+    for (long long k = 0; k < c->ncell; ++k)
+      if (!(n_cell[k] >= 0) || !std::isfinite(n_cell[k]))
+        return fail(c, DG2_EINVAL, "Manning values must be finite and >= 0");
+    if (!c->n) {
+      dg2_status s = alloc(c, &c->n, (size_t)c->P * c->esz, "manning");
+      if (s != DG2_OK) return s;
+    }
+    dg2_status s = upload(c, c->n, n_cell, c->ncell);
+    if (s != DG2_OK) return s;
+    c->has_ncell = true;
+  } else {
+    if (!(n_uniform >= 0) || !std::isfinite(n_uniform))
+      return fail(c, DG2_EINVAL, "Manning value must be finite and >= 0");
+    c->has_ncell = false;
+    c->n_uniform = n_uniform;
+  }
+  return DG2_OK;
+}
+
+dg2_status dg2_set_state(dg2_ctx *c, const double *m, double t) {
+  if (!c) return DG2_EINVAL;
+  if (!m) return fail(c, DG2_EINVAL, "modes9 is NULL");
+  if (!std::isfinite(t)) return fail(c, DG2_EINVAL, "t must be finite");
+  const size_t n = (size_t)c->ncell;
+  if (!finite_all(m, 9 * n)) return fail(c, DG2_EINVAL, "state has non-finite values");
+  for (size_t k = 0; k < n; ++k)
+    if (m[k] < 0) return fail(c, DG2_EINVAL, "mean depth h0 must be >= 0");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
+  for (int k = 0; k < 9; ++k) {
+    dg2_status s = upload(c, plane(c->U, c, k), m + k * n, n);
+    if (s != DG2_OK) return s;
+  }
+  dg2_status s = reset_time(c, t);
+  if (s != DG2_OK) return s;
+  return prime(c);
+}
+
+dg2_status dg2_set_initial_corners(dg2_ctx *c, const double *surf, int32_t is_eta, const double *qx,
+                                   const double *qy) {
+  if (!c) return DG2_EINVAL;
+  if (!surf) return fail(c, DG2_EINVAL, "surface is NULL");
+  const int nx = c->cfg.nx, ny = c->cfg.ny;
+  const size_t nc = (size_t)(nx + 1) * (ny + 1), n = (size_t)c->ncell;
+  if (!finite_all(surf, nc) || (qx && !finite_all(qx, nc)) || (qy && !finite_all(qy, nc)))
+    return fail(c, DG2_EINVAL, "initial condition has non-finite values");
+  if (!is_eta)
+    for (size_t k = 0; k < nc; ++k)
+      if (surf[k] < 0) return fail(c, DG2_EINVAL, "depths must be >= 0");
+  std::vector<double> m(9 * n, 0.0);
+  corner_modes(surf, nx, ny, &m[0], &m[n], &m[2 * n]);
+  if (is_eta) {
+    for (size_t k = 0; k < n; ++k) {
+      double h0 = m[k] - c->z0[k], h1 = m[n + k] - c->z1x[k], h2 = m[2 * n + k] - c->z1y[k];
+      if (h0 < 0) h0 = h1 = h2 = 0.0;
+      m[k] = h0;
+      m[n + k] = h1;
+      m[2 * n + k] = h2;
+    }
+  }
+  if (qx) corner_modes(qx, nx, ny, &m[3 * n], &m[4 * n], &m[5 * n]);
+  if (qy) corner_modes(qy, nx, ny, &m[6 * n], &m[7 * n], &m[8 * n]);
+  return dg2_set_state(c, m.data(), 0.0);
+}
+
+dg2_status dg2_get_state(dg2_ctx *c, double *m, double *t, int64_t *step, double *last_dt) {
+  if (!c) return DG2_EINVAL;
+  const size_t n = (size_t)c->ncell;
+  if (m) {
+    for (int k = 0; k < 9; ++k) {
+      dg2_status s = download(c, m + k * n, plane(c->U, c, k), n);
+      if (s != DG2_OK) return s;
+    }
+  }
+  dg2_status s = read_ctrl(c);
+  if (s != DG2_OK) return s;
+  if (t) *t = c->hctrl->t;
+  if (step) *step = c->hctrl->step;
+  if (last_dt) *last_dt = c->hctrl->last_dt;
+  return latched(c);
+}
+
+dg2_status dg2_set_boundary(dg2_ctx *c, int32_t side, int32_t bc, int32_t first, int32_t last) {
+  if (!c) return DG2_EINVAL;
+  if (side < 0 || side > 3) return fail(c, DG2_EINVAL, "bad side");
+  const int len = (side == DG2_WEST || side == DG2_EAST) ? c->cfg.ny : c->cfg.nx;
+  if (bc == DG2_BC_WALL) {
+    c->inflow[side] = false;
+  } else if (bc == DG2_BC_INFLOW_Q) {
+    if (first < 0 || last >= len || first > last) return fail(c, DG2_EINVAL, "bad segment");
+    c->inflow[side] = true;
+    c->seg_first[side] = first;
+    c->seg_last[side] = last;
+  } else {
+    return fail(c, DG2_EINVAL, "bad boundary type");
+  }
+  HIPCHK(c, queue_plan(c, kPlanOnly), "plan");
+  return DG2_OK;
+}
+
+dg2_status dg2_set_inflow_hydrograph(dg2_ctx *c, int32_t side, const double *t, const double *Q,
+                                     int32_t n) {
+  if (!c) return DG2_EINVAL;
+  if (side < 0 || side > 3) return fail(c, DG2_EINVAL, "bad side");
+  if (!t || !Q || n < 1) return fail(c, DG2_EINVAL, "need n >= 1 samples");
+  for (int k = 0; k < n; ++k) {
+    if (!std::isfinite(t[k]) || !std::isfinite(Q[k]) || Q[k] < 0)
+      return fail(c, DG2_EINVAL, "hydrograph values must be finite and Q >= 0");
+    if (k > 0 && !(t[k] > t[k - 1])) return fail(c, DG2_EINVAL, "hydrograph times must increase");
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
+  if (c->hyd_t[side]) (void)hipFree(c->hyd_t[side]);
+  if (c->hyd_Q[side]) (void)hipFree(c->hyd_Q[side]);
+  c->hyd_t[side] = c->hyd_Q[side] = nullptr;
+  c->nhyd[side] = 0;
+  HIPCHK(c, hipMalloc((void **)&c->hyd_t[side], n * 8), "hydrograph");
+  HIPCHK(c, hipMalloc((void **)&c->hyd_Q[side], n * 8), "hydrograph");
+  HIPCHK(c, hipMemcpy(c->hyd_t[side], t, n * 8, hipMemcpyHostToDevice), "hydrograph");
+  HIPCHK(c, hipMemcpy(c->hyd_Q[side], Q, n * 8, hipMemcpyHostToDevice), "hydrograph");
+  c->nhyd[side] = n;
+  HIPCHK(c, queue_plan(c, kPlanOnly), "plan");
+  return DG2_OK;
+}
+
+dg2_status dg2_set_rainfall(dg2_ctx *c, double rate, double tb, double te) {
+  if (!c) return DG2_EINVAL;
+  if (!(rate >= 0) || !std::isfinite(rate) || !std::isfinite(tb) || !std::isfinite(te) || te < tb)
+    return fail(c, DG2_EINVAL, "rain needs rate >= 0 and t_begin <= t_end");
+  c->rain_rate = rate;
+  c->rain_tb = tb;
+  c->rain_te = te;
+  HIPCHK(c, queue_plan(c, kPlanOnly), "plan");
+  return DG2_OK;
+}
+
+dg2_status dg2_set_fixed_dt(dg2_ctx *c, double dt) {
+  if (!c) return DG2_EINVAL;
+  if (!std::isfinite(dt)) return fail(c, DG2_EINVAL, "dt must be finite");
+  c->fixed_dt = dt > 0 ? dt : 0.0;
+  HIPCHK(c, queue_plan(c, kPlanOnly), "plan");
+  return DG2_OK;
+}
+
+dg2_status dg2_set_gauges(dg2_ctx *c, const double *xy, int32_t n, int32_t cap) {
+  if (!c) return DG2_EINVAL;
+  if (n < 0 || n > kMaxGauges) return fail(c, DG2_EINVAL, "0 <= n <= 64 gauges");
+  if (n > 0 && !xy) return fail(c, DG2_EINVAL, "xy is NULL");
+  const dg2_config &g = c->cfg;
+  std::vector<int> cell(n);
+  std::vector<double> xi(n), ze(n), zp(n);
+  for (int k = 0; k < n; ++k) {
+    const double x = xy[2 * k], y = xy[2 * k + 1];
+    if (!(x >= g.x0 && x <= g.x0 + g.nx * g.dx && y >= g.y0 && y <= g.y0 + g.ny * g.dy))
+      return fail(c, DG2_EINVAL, "gauge outside the domain");
+    int i = (int)std::floor((x - g.x0) / g.dx), j = (int)std::floor((y - g.y0) / g.dy);
+    i = i < 0 ? 0 : (i >= g.nx ? g.nx - 1 : i);
+    j = j < 0 ? 0 : (j >= g.ny ? g.ny - 1 : j);
+    cell[k] = j * g.nx + i;
+    xi[k] = (x - (g.x0 + (i + 0.5) * g.dx)) / (0.5 * g.dx);
+    ze[k] = (y - (g.y0 + (j + 0.5) * g.dy)) / (0.5 * g.dy);
+    const size_t cc = cell[k];
+    zp[k] = c->z0[cc] + xi[k] * c->z1x[cc] + ze[k] * c->z1y[cc];
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
+  void *old[] = {c->g_cell, c->g_xi, c->g_zeta, c->g_z, c->g_buf, c->g_t};
+  for (void *b : old)
+    if (b) (void)hipFree(b);
+  c->g_cell = nullptr;
+  c->g_xi = c->g_zeta = c->g_z = c->g_buf = nullptr;
+  c->g_t = nullptr;
+  c->ng = 0;
+  c->gcap = 0;
+  if (n > 0) {
+    const int capv = cap > 0 ? cap : 65536;
+    dg2_status s;
+    if ((s = alloc(c, (void **)&c->g_cell, n * sizeof(int), "gauges")) != DG2_OK) return s;
+    if ((s = alloc(c, &c->g_xi, n * c->esz, "gauges")) != DG2_OK) return s;
+    if ((s = alloc(c, &c->g_zeta, n * c->esz, "gauges")) != DG2_OK) return s;
+    if ((s = alloc(c, &c->g_z, n * c->esz, "gauges")) != DG2_OK) return s;
+    if ((s = alloc(c, &c->g_buf, (size_t)capv * n * 4 * c->esz, "gauge record")) != DG2_OK) return s;
+    if ((s = alloc(c, (void **)&c->g_t, (size_t)capv * sizeof(double), "gauge record")) != DG2_OK)
+      return s;
+    HIPCHK(c, hipMemcpy(c->g_cell, cell.data(), n * sizeof(int), hipMemcpyHostToDevice), "gauges");
+    if ((s = upload(c, c->g_xi, xi.data(), n)) != DG2_OK) return s;
+    if ((s = upload(c, c->g_zeta, ze.data(), n)) != DG2_OK) return s;
+    if ((s = upload(c, c->g_z, zp.data(), n)) != DG2_OK) return s;
+    c->ng = n;
+    c->gcap = capv;
+  }
+  // restart the record
+  dg2_status s = read_ctrl(c);
+  if (s != DG2_OK) return s;
+  const long long zero = 0;
+  HIPCHK(c, hipMemcpyAsync(&c->ctrl->gauge_written, &zero, sizeof(zero), hipMemcpyHostToDevice,
+                           c->stream), "gauges");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "gauges");
+  c->g_read = 0;
+  return DG2_OK;
+}
+
+dg2_status dg2_step(dg2_ctx *c, int32_t nsteps) {
+  if (!c) return DG2_EINVAL;
+  if (nsteps < 0) return fail(c, DG2_EINVAL, "nsteps must be >= 0");
+  HIPCHK(c, queue_plan(c, kPlanOnly, std::numeric_limits<double>::infinity(), 1), "plan");
+  for (int k = 0; k < nsteps; ++k) {
+    dg2_status s = queue_step(c);
+    if (s != DG2_OK) return s;
+  }
+  return DG2_OK;
+}
+
+dg2_status dg2_run_to(dg2_ctx *c, double T) {
+  if (!c) return DG2_EINVAL;
+  if (!std::isfinite(T)) return fail(c, DG2_EINVAL, "T must be finite");
+  HIPCHK(c, queue_plan(c, kPlanOnly, T, 1), "plan");
+  dg2_status s = read_ctrl(c);
+  if (s != DG2_OK) return s;
+  if ((s = latched(c)) != DG2_OK) return s;
+  if (!(c->hctrl->t < T)) return DG2_OK;
+  // queue chunks of steps; the chunk after the one that reaches T only holds
+  // idle steps (dt = 0) that return at once.
+  const int chunk = 32;
+  long long guard = 0;
+  hipEvent_t ev;
+  HIPCHK(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+  Ctrl *snap = c->hctrl;
+  dg2_status st = DG2_OK;
+  for (;;) {
+    for (int k = 0; k < chunk; ++k) {
+      if ((st = queue_step(c)) != DG2_OK) break;
+    }
+    if (st != DG2_OK) break;
+    hipError_t e = hipMemcpyAsync(snap, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev);
+    if (e != hipSuccess) {
+      st = hipfail(c, e, "run_to");
+      break;
+    }
+    if (snap->flags) {
+      st = latched(c);
+      break;
+    }
+    if (!(snap->t < T)) break;
+    if (!(snap->dt > 0)) {
+      st = fail(c, DG2_ENUMERIC, "time step collapsed to zero before reaching T");
+      break;
+    }
+    guard += chunk;
+    if (guard > (1ll << 31)) {
+      st = fail(c, DG2_ESTATE, "run_to exceeded 2^31 steps");
+      break;
+    }
+  }
+  (void)hipEventDestroy(ev);
+  return st;
+}
+
+dg2_status dg2_sync(dg2_ctx *c) {
+  if (!c) return DG2_EINVAL;
+  dg2_status s = read_ctrl(c);
+  if (s != DG2_OK) return s;
+  return latched(c);
+}
+
+dg2_status dg2_read_gauges(dg2_ctx *c, double *out, double *t, int32_t max_samples, int32_t *ns) {
+  if (!c) return DG2_EINVAL;
+  if (ns) *ns = 0;
+  if (c->ng == 0) return fail(c, DG2_ESTATE, "no gauges set");
+  if (max_samples < 0 || (max_samples > 0 && (!out || !t)))
+    return fail(c, DG2_EINVAL, "need output buffers");
+  dg2_status s = read_ctrl(c);
+  if (s != DG2_OK) return s;
+  const long long written = c->hctrl->gauge_written;
+  long long avail = written - c->g_read;
+  bool lost = false;
+  if (avail > c->gcap) {
+    c->g_read = written - c->gcap;
+    avail = c->gcap;
+    lost = true;
+  }
+  const long long take = avail < max_samples ? avail : max_samples;
+  const int ng = c->ng;
+  const size_t per = (size_t)ng * 4;
+  std::vector<double> tmp(per);
+  for (long long k = 0; k < take; ++k) {
+    const long long slot = (c->g_read + k) % c->gcap;
+    s = download(c, tmp.data(), (char *)c->g_buf + slot * per * c->esz, per);
+    if (s != DG2_OK) return s;
+    std::memcpy(out + k * per, tmp.data(), per * sizeof(double));
+    HIPCHK(c, hipMemcpy(t + k, c->g_t + slot, sizeof(double), hipMemcpyDeviceToHost), "gauge t");
+  }
+  c->g_read += take;
+  if (ns) *ns = (int32_t)take;
+  if ((s = latched(c)) != DG2_OK) return s;
+  if (lost) return fail(c, DG2_ESTATE, "gauge record overflowed; oldest samples lost");
+  return DG2_OK;
+}
+
+dg2_status dg2_diagnostics(dg2_ctx *c, double *mass, double *energy, double *min_h) {
+  if (!c) return DG2_EINVAL;
+  hipError_t e = c->f32 ? launch_diag<float>(scen<float>(c), consts(c), c->diag_part, kDiagBlocks,
+                                             c->diag_out, c->stream)
+                        : launch_diag<double>(scen<double>(c), consts(c), c->diag_part, kDiagBlocks,
+                                              c->diag_out, c->stream);
+  HIPCHK(c, e, "diagnostics");
+  double h[4];
+  HIPCHK(c, hipMemcpyAsync(h, c->diag_out, sizeof(h), hipMemcpyDeviceToHost, c->stream), "diag");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "diag");
+  const double area = c->cfg.dx * c->cfg.dy;
+  if (mass) *mass = h[0] * area;
+  if (energy) *energy = h[1] * 0.25 * area;
+  if (min_h) *min_h = h[2];
+  dg2_status s = read_ctrl(c);
+  if (s != DG2_OK) return s;
+  if (h[3] > 0) return fail(c, DG2_ENUMERIC, "NaN in the state");
+  return latched(c);
+}
+
+dg2_status dg2_time_kernels(dg2_ctx *c, int32_t nsteps, double *ms1, double *ms2, double *msstep) {
+  if (!c) return DG2_EINVAL;
+  if (nsteps < 1) return fail(c, DG2_EINVAL, "nsteps must be >= 1");
+  HIPCHK(c, queue_plan(c, kPlanOnly, std::numeric_limits<double>::infinity(), 1), "plan");
+  std::vector<hipEvent_t> ev(3 * nsteps + 1);
+  for (auto &e : ev) HIPCHK(c, hipEventCreate(&e), "event");
+  dg2_status st = DG2_OK;
+  for (int k = 0; k < nsteps && st == DG2_OK; ++k) st = queue_step(c, &ev[3 * k]);
+  if (st == DG2_OK) {
+    hipError_t e = hipEventRecord(ev[3 * nsteps], c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[3 * nsteps]);
+    if (e != hipSuccess) st = hipfail(c, e, "timing");
+  }
+  double a = 0, b = 0, w = 0;
+  if (st == DG2_OK) {
+    for (int k = 0; k < nsteps; ++k) {
+      float t1 = 0, t2 = 0;
+      (void)hipEventElapsedTime(&t1, ev[3 * k], ev[3 * k + 1]);
+      (void)hipEventElapsedTime(&t2, ev[3 * k + 1], ev[3 * k + 2]);
+      a += t1;
+      b += t2;
+    }
+    float tw = 0;
+    (void)hipEventElapsedTime(&tw, ev[0], ev[3 * nsteps]);
+    w = tw;
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  if (st != DG2_OK) return st;
+  if (ms1) *ms1 = a / nsteps;
+  if (ms2) *ms2 = b / nsteps;
+  if (msstep) *msstep = w / nsteps;
+  return dg2_sync(c);
+}
+
+dg2_status dg2_set_launch(dg2_ctx *c, int32_t rows, int32_t wpb) {
+  if (!c) return DG2_EINVAL;
+  if (wpb != 1 && wpb != 2 && wpb != 4) return fail(c, DG2_EINVAL, "waves per block must be 1, 2 or 4");
+  c->R_user = rows > 0 ? rows : 0;
+  c->wpb_user = wpb;
+  return DG2_OK;
+}
+
+dg2_status dg2_autotune(dg2_ctx *c, double budget_ms, int32_t *rows) {
+  if (!c) return DG2_EINVAL;
+  if (!(budget_ms > 0)) return fail(c, DG2_EINVAL, "budget must be > 0");
+  const size_t bytes = 9 * (size_t)c->P * c->esz;
+  void *save = nullptr;
+  HIPCHK(c, hipMalloc(&save, bytes), "autotune");
+  HIPCHK(c, hipMemcpyAsync(save, c->U, bytes, hipMemcpyDeviceToDevice, c->stream), "autotune");
+  dg2_status s = read_ctrl(c);
+  if (s != DG2_OK) {
+    (void)hipFree(save);
+    return s;
+  }
+  const Ctrl keep = *c->hctrl;
+  const int cand[] = {2, 4, 8, 16, 32, 64, 128};
+  double best = 1e300;
+  int bestR = launch_of(c).R;
+  double spent = 0;
+  for (int R : cand) {
+    if (R > c->cfg.ny) continue;
+    c->R_user = R;
+    double ms = 0;
+    s = dg2_time_kernels(c, 3, nullptr, nullptr, &ms);
+    HIPCHK(c, hipMemcpyAsync(c->U, save, bytes, hipMemcpyDeviceToDevice, c->stream), "autotune");
+    *c->hctrl = keep;
+    HIPCHK(c, hipMemcpyAsync(c->ctrl, c->hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, c->stream), "autotune");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "autotune");
+    if (s != DG2_OK) break;
+    if (ms < best) {
+      best = ms;
+      bestR = R;
+    }
+    spent += 4 * ms;
+    if (spent > budget_ms) break;
+  }
+  (void)hipFree(save);
+  c->R_user = bestR;
+  if (rows) *rows = bestR;
+  return s;
+}
+
+dg2_status dg2_state_layout(const dg2_ctx *c, size_t *bytes, size_t *stride) {
+  if (!c) return DG2_EINVAL;
+  if (bytes) *bytes = 9 * (size_t)c->P * c->esz;
+  if (stride) *stride = (size_t)c->P;
+  return DG2_OK;
+}
+
+dg2_status dg2_bind_device_state(dg2_ctx *c, void *ptr, size_t bytes) {
+  if (!c) return DG2_EINVAL;
+  const size_t need = 9 * (size_t)c->P * c->esz;
+  void *target = ptr ? ptr : c->U_own;
+  if (ptr && (bytes < need || ((uintptr_t)ptr & 255)))
+    return fail(c, DG2_EINVAL, "device buffer too small or not 256-byte aligned");
+  if (target != c->U)
+    HIPCHK(c, hipMemcpyAsync(target, c->U, need, hipMemcpyDeviceToDevice, c->stream), "bind");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "bind");
+  c->U = target;
+  return DG2_OK;
+}
+
+}  // extern "C"

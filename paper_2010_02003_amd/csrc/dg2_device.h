@@ -1,0 +1,241 @@
+// Device-side building blocks of the DG2 step (gfx950, wave64).
+//
+// Pointwise formulas of Sec. 2.1.2-2.1.3 of the paper: dummy limits, the
+// HLL face flux, the physical flux at Gauss points and the implicit friction
+// split.  Templated on the arithmetic type (double or float).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dg2 {
+
+constexpr double kInvSqrt3 = 0.57735026918962576451;   // Gauss points at +-1/sqrt(3), Eq. (4b-c)
+constexpr double kHalfSqrt3 = 0.86602540378443864676;  // slope from two Gauss values
+constexpr uint64_t kInfBits = 0x7FF0000000000000ull;   // +inf as double bits
+
+// Device-resident step control.  One per context (or per scenario in a
+// batch).  Only the single-thread plan kernel writes t, dt, rain and qin;
+// the stage kernels read them, so a queued step never needs the host.
+struct Ctrl {
+  double t;            // time of the current state
+  double dt;           // size of the pending step, <= 0: idle
+  double t_end;        // run-to target, +inf when none
+  double rain;         // rain depth added by the pending step
+  double qin[4][2];    // unit inflow per side at the two stage times
+  double cflmin;       // min_c m_c of the current state (+inf: nothing wet)
+  double last_dt;      // size of the last completed step
+  long long step;      // completed steps
+  unsigned long long minbits;  // running min of m_c for the next step (double bits)
+  unsigned int flags;  // bit 0: NaN, bit 1: negative mean depth
+  unsigned int pad;
+  long long gauge_written;  // samples recorded since the gauge record was reset
+};
+
+enum : unsigned { kFlagNaN = 1u, kFlagNegative = 2u };
+
+// Parameters of the step planner (host-side constants of one context).
+struct PlanArgs {
+  double cfl, dt_max, fixed_dt;
+  double rain_rate, rain_tb, rain_te;
+  int nhyd[4];
+  const double *hyd_t[4];
+  const double *hyd_Q[4];
+  double seg_len[4];
+  int ng;          // gauges (for the time record)
+  int gauge_cap;
+  double *gauge_t;
+};
+
+template <typename real> __device__ __forceinline__ real dsqrt(real x);
+template <> __device__ __forceinline__ double dsqrt<double>(double x) { return sqrt(x); }
+template <> __device__ __forceinline__ float dsqrt<float>(float x) { return sqrtf(x); }
+template <typename real> __device__ __forceinline__ real drcbrt(real x);
+template <> __device__ __forceinline__ double drcbrt<double>(double x) { return rcbrt(x); }
+template <> __device__ __forceinline__ float drcbrt<float>(float x) { return rcbrtf(x); }
+template <typename real> __device__ __forceinline__ real dcbrt(real x);
+template <> __device__ __forceinline__ double dcbrt<double>(double x) { return cbrt(x); }
+template <> __device__ __forceinline__ float dcbrt<float>(float x) { return cbrtf(x); }
+
+template <typename real> __device__ __forceinline__ real dmax(real a, real b) { return a > b ? a : b; }
+template <typename real> __device__ __forceinline__ real dmin(real a, real b) { return a < b ? a : b; }
+
+// Positivity-preserving dummy limit (Sec. 2.1.2): h* = max(0, h), velocities
+// q/h above the drying tolerance and zero otherwise.
+template <typename real>
+__device__ __forceinline__ void dummy_limit(real h, real qx, real qy, real tol, real &hs, real &u,
+                                            real &v) {
+  hs = h > real(0) ? h : real(0);
+  if (h > tol) {
+    const real r = real(1) / h;
+    u = qx * r;
+    v = qy * r;
+  } else {
+    u = real(0);
+    v = real(0);
+  }
+}
+
+// HLL flux through a face with normal velocity u and tangential velocity v.
+// Wave speeds: Toro's two-rarefaction estimates, dry-bed front speeds when a
+// side is dry, zero flux when both are.  F = [h u, h u^2 + g h^2/2, h u v].
+template <typename real>
+__device__ __forceinline__ void hll(real hL, real uL, real vL, real hR, real uR, real vR, real g,
+                                    real tol, real &F0, real &F1, real &F2) {
+  const bool dryL = hL <= tol, dryR = hR <= tol;
+  if (dryL && dryR) {
+    F0 = F1 = F2 = real(0);
+    return;
+  }
+  const real cL = dsqrt(g * hL), cR = dsqrt(g * hR);
+  const real us = real(0.5) * (uL + uR) + cL - cR;
+  const real cs = real(0.5) * (cL + cR) + real(0.25) * (uL - uR);
+  const real sL = dryL ? uR - real(2) * cR : dmin(uL - cL, us - cs);
+  const real sR = dryR ? uL + real(2) * cL : dmax(uR + cR, us + cs);
+  const real qL = hL * uL, qR = hR * uR;
+  const real FL0 = qL, FL1 = qL * uL + real(0.5) * g * hL * hL, FL2 = qL * vL;
+  const real FR0 = qR, FR1 = qR * uR + real(0.5) * g * hR * hR, FR2 = qR * vR;
+  if (sL >= real(0)) {
+    F0 = FL0; F1 = FL1; F2 = FL2;
+  } else if (sR <= real(0)) {
+    F0 = FR0; F1 = FR1; F2 = FR2;
+  } else {
+    const real inv = real(1) / (sR - sL);
+    const real ss = sL * sR;
+    F0 = (sR * FL0 - sL * FR0 + ss * (hR - hL)) * inv;
+    F1 = (sR * FL1 - sL * FR1 + ss * (qR - qL)) * inv;
+    F2 = (sR * FL2 - sL * FR2 + ss * (hR * vR - hL * vL)) * inv;
+  }
+}
+
+// Prescribed discharge q through an inflow face: normal flux components
+// [q, q^2/h_b + g h_b^2/2, 0], h_b = max(inner dummy depth, critical depth).
+template <typename real>
+__device__ __forceinline__ void inflow_flux(real q, real h_inner, real g, real &F0, real &F1) {
+  const real hc = dcbrt(q * q / g);
+  const real hb = dmax(h_inner, hc);
+  F0 = q;
+  F1 = q * q / hb + real(0.5) * g * hb * hb;
+}
+
+// Physical x-flux at a point (Eq. 1), velocity zeroed at or below tol.
+template <typename real>
+__device__ __forceinline__ void flux_x(real h, real qx, real qy, real g, real tol, real &F0,
+                                       real &F1, real &F2) {
+  const real hp = h > real(0) ? h : real(0);
+  const real pres = real(0.5) * g * hp * hp;
+  if (h > tol) {
+    const real r = real(1) / h;
+    const real u = qx * r, v = qy * r;
+    const real q = hp * u;
+    F0 = q;
+    F1 = q * u + pres;
+    F2 = q * v;
+  } else {
+    F0 = real(0);
+    F1 = pres;
+    F2 = real(0);
+  }
+}
+
+// Physical y-flux at a point, returned as [mass, x-momentum, y-momentum].
+template <typename real>
+__device__ __forceinline__ void flux_y(real h, real qx, real qy, real g, real tol, real &G0,
+                                       real &G1, real &G2) {
+  const real hp = h > real(0) ? h : real(0);
+  const real pres = real(0.5) * g * hp * hp;
+  if (h > tol) {
+    const real r = real(1) / h;
+    const real u = qx * r, v = qy * r;
+    const real q = hp * v;
+    G0 = q;
+    G1 = q * u;
+    G2 = q * v + pres;
+  } else {
+    G0 = real(0);
+    G1 = real(0);
+    G2 = pres;
+  }
+}
+
+// Linearised-implicit friction increment at one point: with
+// b = dt g n^2 h^(-7/3),  dq_x = -b q_x |q|^2 / (|q| + b (2 q_x^2 + q_y^2)),
+// which equals dt S_f/(1 - dt dS_f/dq) for S_f = -C_f u|V|, C_f = g n^2 h^(-1/3).
+template <typename real>
+__device__ __forceinline__ void friction_point(real h, real qx, real qy, real gn2dt, real tol,
+                                               real &dqx, real &dqy) {
+  const real qq = qx * qx + qy * qy;
+  if (h > tol && qq > real(0)) {
+    const real rc = drcbrt(h);
+    const real rc2 = rc * rc;
+    const real b = gn2dt * (rc2 * rc2) * (rc2 * rc);
+    const real qm = dsqrt(qq);
+    const real bq = b * qq;
+    dqx = -bq * qx / (qm + b * (real(2) * qx * qx + qy * qy));
+    dqy = -bq * qy / (qm + b * (qx * qx + real(2) * qy * qy));
+  } else {
+    dqx = real(0);
+    dqy = real(0);
+  }
+}
+
+// Friction split on a planar element (Sec. 2.1.3, Fig. 1): increments at the
+// centre and at G_x+-, G_y+- = U0 +- U1/sqrt(3); the centre increment goes to
+// the mean discharges, sqrt(3)/2 times the Gauss difference to the slopes.
+// W: [h0,h1x,h1y,qx0,qx1x,qx1y,qy0,qy1x,qy1y].
+template <typename real>
+__device__ __forceinline__ void apply_friction(real *W, real gn2dt, real tol) {
+  if (!(gn2dt > real(0))) return;
+  const real is3 = real(kInvSqrt3), hs3 = real(kHalfSqrt3);
+  real cx, cy, pxx, pxy, mxx, mxy, pyx, pyy, myx, myy;
+  friction_point(W[0], W[3], W[6], gn2dt, tol, cx, cy);
+  friction_point(W[0] + W[1] * is3, W[3] + W[4] * is3, W[6] + W[7] * is3, gn2dt, tol, pxx, pxy);
+  friction_point(W[0] - W[1] * is3, W[3] - W[4] * is3, W[6] - W[7] * is3, gn2dt, tol, mxx, mxy);
+  friction_point(W[0] + W[2] * is3, W[3] + W[5] * is3, W[6] + W[8] * is3, gn2dt, tol, pyx, pyy);
+  friction_point(W[0] - W[2] * is3, W[3] - W[5] * is3, W[6] - W[8] * is3, gn2dt, tol, myx, myy);
+  W[3] += cx;
+  W[4] += hs3 * (pxx - mxx);
+  W[5] += hs3 * (pyx - myx);
+  W[6] += cy;
+  W[7] += hs3 * (pxy - mxy);
+  W[8] += hs3 * (pyy - myy);
+}
+
+// Mirror ghost across an x-wall (mx) and/or a y-wall (my): the normal
+// discharge is odd, h and the tangential discharge are even.
+template <typename real>
+__device__ __forceinline__ void mirror(real *W, bool mx, bool my) {
+  if (mx) {
+    W[1] = -W[1];
+    W[3] = -W[3];
+    W[5] = -W[5];
+    W[7] = -W[7];
+  }
+  if (my) {
+    W[2] = -W[2];
+    W[5] = -W[5];
+    W[6] = -W[6];
+    W[7] = -W[7];
+  }
+}
+
+// Courant candidate m_c = min(dx/(|u|+c), dy/(|v|+c)) of a wet mean state.
+template <typename real>
+__device__ __forceinline__ double cfl_candidate(real h0, real qx0, real qy0, real g, real tol,
+                                                real dx, real dy) {
+  if (!(h0 > tol)) return __longlong_as_double((long long)kInfBits);
+  const real u = fabs(qx0 / h0), v = fabs(qy0 / h0);
+  const real c = dsqrt(g * h0);
+  const real m = dmin(dx / (u + c), dy / (v + c));
+  return (double)m;
+}
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned long long o = __shfl_xor(v, off, 64);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+}  // namespace dg2

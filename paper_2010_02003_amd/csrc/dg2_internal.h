@@ -1,0 +1,65 @@
+// Internal interface between the C-ABI runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dg2_device.h"
+
+namespace dg2 {
+
+// Geometry and per-context constants of one scenario, as the stage kernels
+// see it.  All device pointers index planes of ``P`` elements.
+template <typename real>
+struct Scen {
+  const real *U;    // 9 planes: state at the start of the step
+  real *U1;         // 9 planes: stage-1 result
+  real *W1;         // 9 planes: limited stage-1 input (DG2-LL only)
+  const real *z;    // 3 planes: z0, z1x, z1y
+  const real *n;    // per-cell Manning or nullptr
+  real n_uniform;
+  Ctrl *ctrl;
+  int nx, ny;
+  long long P;
+  real dx, dy, idx, idy;
+  int seg_first[4], seg_last[4];  // inflow segment per side (first > last: none)
+  // gauges
+  int ng;
+  const int *g_cell;
+  const real *g_xi, *g_zeta, *g_z;
+  real *g_buf;
+  int g_cap;
+};
+
+struct Consts {
+  double g, tol, theta;
+};
+
+struct Launch {
+  int R;        // rows per wavefront
+  int wpb;      // wavefronts per workgroup
+  int nstrips;  // ceil(nx / cols-per-strip)
+  int nitems;   // nstrips * ceil(ny / R)
+};
+
+constexpr int kStripNL = 62;  // output columns per wavefront (halo 1)
+constexpr int kStripLL = 60;  // output columns per wavefront (halo 2)
+
+Launch make_launch(int nx, int ny, int variant, int R, int wpb);
+
+template <typename real>
+hipError_t launch_stage(int stage, int variant, const Scen<real> &s, const Consts &c,
+                        const Launch &L, hipStream_t st);
+
+hipError_t launch_plan(Ctrl *ctrl, const PlanArgs &p, int mode, double t_end, int set_tend,
+                       hipStream_t st);
+
+template <typename real>
+hipError_t launch_cfl(const Scen<real> &s, const Consts &c, hipStream_t st);
+
+template <typename real>
+hipError_t launch_diag(const Scen<real> &s, const Consts &c, double *partials, int nblocks,
+                       double *out4, hipStream_t st);
+
+enum PlanMode { kPlanOnly = 0, kPlanFromMin = 1, kPlanFinishStep = 2 };
+
+}  // namespace dg2

@@ -1,0 +1,497 @@
+// HIP kernels of the DG2 step for gfx950 (CDNA4, wave64).
+//
+// Stage kernels (one launch per RK stage, Sec. 2.1.2): every wavefront owns a
+// strip of output columns plus one halo column on each side and marches up
+// R rows of the grid.  Each lane holds one cell column.  For every row the
+// lane builds the stage input (rain + friction split of Sec. 2.1.3 in stage
+// 1), its four dummy face limits (Sec. 2.1.2), the north-face flux with the
+// row above (kept in registers for the next row as its south face) and the
+// east-face flux with the neighbouring lane; the west-face flux arrives from
+// the lane to the west by a cross-lane shuffle.  Every face flux is
+// evaluated once, nothing goes through LDS, and each state plane is read
+// once per stage with unit-stride, wave-wide loads (structure of arrays).
+//
+// Stage 2 writes U^{n+1} in place over U^n: a lane reads U^n only at the
+// cell it writes, and halo lanes read only the stage-1 planes.  Its tail
+// folds the Courant candidate of every new cell into a wave minimum and one
+// atomic per wavefront; a single-thread plan kernel then turns the minimum
+// into the next step size on the device, so queued steps never wait for
+// the host.
+#include <hip/hip_runtime.h>
+
+#include "dg2_internal.h"
+
+namespace dg2 {
+
+template <typename real>
+struct Row {
+  real W[9];
+  real eh, eu, ev, er;  // east face, west ('-') side: dummy h*, u, v and raw depth
+  real wh, wu, wv;      // west face, east ('+') side
+  real nh, nu, nv, nr;  // north face, south ('-') side, raw depth
+  real sh, su, sv;      // south face, north ('+') side
+};
+
+template <typename real>
+__device__ __forceinline__ void row_limits(Row<real> &r, real tol) {
+  const real *W = r.W;
+  r.er = W[0] + W[1];
+  dummy_limit(r.er, W[3] + W[4], W[6] + W[7], tol, r.eh, r.eu, r.ev);
+  dummy_limit(W[0] - W[1], W[3] - W[4], W[6] - W[7], tol, r.wh, r.wu, r.wv);
+  r.nr = W[0] + W[2];
+  dummy_limit(r.nr, W[3] + W[5], W[6] + W[8], tol, r.nh, r.nu, r.nv);
+  dummy_limit(W[0] - W[2], W[3] - W[5], W[6] - W[8], tol, r.sh, r.su, r.sv);
+}
+
+// Flux through the y-face between a lower row and the row above it, as
+// [mass, x-momentum, y-momentum].
+template <typename real>
+__device__ __forceinline__ void y_face(const Row<real> &lo, const Row<real> &hi, real g, real tol,
+                                       real &G0, real &G1, real &G2) {
+  real m, fn, ft;
+  hll(lo.nh, lo.nv, lo.nu, hi.sh, hi.sv, hi.su, g, tol, m, fn, ft);
+  G0 = m;
+  G1 = ft;
+  G2 = fn;
+}
+
+// One row of the stage input at grid row r for the lane's column: loads the
+// 9 planes (clamped into the grid), mirrors ghosts, adds rain and applies
+// the friction split in stage 1, and forms the dummy face limits.
+template <typename real, int STAGE>
+__device__ __forceinline__ void load_row(const Scen<real> &s, const real *src, int r, int ci,
+                                         bool mx, real rain, real gdt, real tol, Row<real> &row) {
+  const int rs = r < 0 ? 0 : (r >= s.ny ? s.ny - 1 : r);
+  const bool my = (r < 0) || (r >= s.ny);
+  const long long idx = (long long)rs * s.nx + ci;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) row.W[k] = src[k * s.P + idx];
+  real n = s.n_uniform;
+  if (STAGE == 1 && s.n) n = s.n[idx];
+  mirror(row.W, mx, my);
+  if (STAGE == 1) {
+    row.W[0] += rain;
+    apply_friction(row.W, gdt * n * n, tol);
+  }
+  row_limits(row, tol);
+}
+
+template <typename real, int STAGE>
+__global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch L) {
+  const int lane = threadIdx.x & 63;
+  const int item = blockIdx.x * L.wpb + (threadIdx.x >> 6);
+  if (item >= L.nitems) return;
+  const double dtd = s.ctrl->dt;
+  if (!(dtd > 0.0)) return;
+
+  const real dt = (real)dtd, g = (real)c.g, tol = (real)c.tol;
+  const real half = real(0.5), is3 = real(kInvSqrt3), two_g = real(2) * g;
+  const real tg3 = real(2) * g / real(3);
+  const int strip = item % L.nstrips, seg = item / L.nstrips;
+  const int i = strip * kStripNL + lane - 1;
+  const int j0 = seg * L.R, j1 = min(j0 + L.R, s.ny);
+  const bool own = lane >= 1 && lane <= kStripNL && i < s.nx;
+  const int ci = i < 0 ? 0 : (i >= s.nx ? s.nx - 1 : i);
+  const bool mx = (i < 0) || (i >= s.nx);
+  const real rain = (real)s.ctrl->rain;
+  const real gdt = g * dt;
+  const real *src = STAGE == 1 ? s.U : s.U1;
+  real *dst = STAGE == 1 ? s.U1 : const_cast<real *>(s.U);
+
+  const int si = STAGE - 1;
+  const real qW = (real)s.ctrl->qin[0][si], qE = (real)s.ctrl->qin[1][si];
+  const real qS = (real)s.ctrl->qin[2][si], qN = (real)s.ctrl->qin[3][si];
+  const bool faceW = (i == -1) && qW != real(0);
+  const bool faceE = (i == s.nx - 1) && qE != real(0);
+  const bool colS = qS != real(0) && i >= s.seg_first[2] && i <= s.seg_last[2];
+  const bool colN = qN != real(0) && i >= s.seg_first[3] && i <= s.seg_last[3];
+
+  // gauges owned by this wavefront
+  unsigned long long gmask = 0;
+  long long gslot = 0;
+  if (STAGE == 2 && s.ng > 0) {
+    const int c0 = strip * kStripNL;
+    for (int k = 0; k < s.ng; ++k) {
+      const int gc = s.g_cell[k];
+      const int gj = gc / s.nx, gi = gc - gj * s.nx;
+      if (gj >= j0 && gj < j1 && gi >= c0 && gi < c0 + kStripNL) gmask |= 1ull << k;
+    }
+    gslot = (s.ctrl->gauge_written % s.g_cap) * s.ng;
+  }
+
+  Row<real> cur, nxt;
+  real GS0, GS1, GS2, dS;
+  {
+    Row<real> prev;
+    load_row<real, STAGE>(s, src, j0 - 1, ci, mx, rain, gdt, tol, prev);
+    load_row<real, STAGE>(s, src, j0, ci, mx, rain, gdt, tol, cur);
+    y_face(prev, cur, g, tol, GS0, GS1, GS2);
+    dS = dmax(real(0), -prev.nr);
+    if (j0 == 0 && colS) {
+      inflow_flux(qS, cur.sh, g, GS0, GS2);
+      GS1 = real(0);
+    }
+  }
+
+  double mloc = __longlong_as_double((long long)kInfBits);
+  unsigned flags = 0;
+
+  for (int j = j0; j < j1; ++j) {
+    load_row<real, STAGE>(s, src, j + 1, ci, mx, rain, gdt, tol, nxt);
+
+    // north face of row j
+    real GN0, GN1, GN2;
+    y_face(cur, nxt, g, tol, GN0, GN1, GN2);
+    const real dN = dmax(real(0), -cur.nr);
+    if (j == s.ny - 1 && colN) {
+      inflow_flux(qN, cur.nh, g, GN0, GN2);
+      GN0 = -GN0;
+      GN1 = real(0);
+    }
+
+    // east face of this lane's cell; the west face comes from the lane to the west
+    const real ph = __shfl_down(cur.wh, 1, 64);
+    const real pu = __shfl_down(cur.wu, 1, 64);
+    const real pv = __shfl_down(cur.wv, 1, 64);
+    real FE0, FE1, FE2;
+    hll(cur.eh, cur.eu, cur.ev, ph, pu, pv, g, tol, FE0, FE1, FE2);
+    if (faceW && j >= s.seg_first[0] && j <= s.seg_last[0]) {
+      inflow_flux(qW, ph, g, FE0, FE1);
+      FE2 = real(0);
+    }
+    if (faceE && j >= s.seg_first[1] && j <= s.seg_last[1]) {
+      inflow_flux(qE, cur.eh, g, FE0, FE1);
+      FE0 = -FE0;
+      FE2 = real(0);
+    }
+    const real dE = dmax(real(0), -cur.er);
+    const real FW0 = __shfl_up(FE0, 1, 64);
+    const real FW1 = __shfl_up(FE1, 1, 64);
+    const real FW2 = __shfl_up(FE2, 1, 64);
+    const real dW = __shfl_up(dE, 1, 64);
+
+    if (own) {
+      const long long cidx = (long long)j * s.nx + i;
+      const real z1x = s.z[s.P + cidx], z1y = s.z[2 * s.P + cidx];
+      real W1[9];
+      if (STAGE == 2) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) W1[k] = s.U[k * s.P + cidx];
+        const real n = s.n ? s.n[cidx] : s.n_uniform;
+        W1[0] += rain;
+        apply_friction(W1, gdt * n * n, tol);
+      }
+      // dummy modes, Eq. (5)
+      const real e1 = cur.eh * cur.eu, e2 = cur.eh * cur.ev;
+      const real w1 = cur.wh * cur.wu, w2 = cur.wh * cur.wv;
+      const real A0 = half * (cur.eh + cur.wh), A1 = half * (e1 + w1), A2 = half * (e2 + w2);
+      const real B0 = half * (cur.eh - cur.wh), B1 = half * (e1 - w1), B2 = half * (e2 - w2);
+      const real n1 = cur.nh * cur.nu, n2 = cur.nh * cur.nv;
+      const real s1 = cur.sh * cur.su, s2 = cur.sh * cur.sv;
+      const real C0 = half * (cur.nh + cur.sh), C1 = half * (n1 + s1), C2 = half * (n2 + s2);
+      const real D0 = half * (cur.nh - cur.sh), D1 = half * (n1 - s1), D2 = half * (n2 - s2);
+      // revised bed slopes: z*_face = z_face - max(0, -h^-) on each face
+      const real zbx = z1x - half * dE + half * dW;
+      const real zby = z1y - half * dN + half * dS;
+      // physical fluxes at the Gauss points
+      real Fp0, Fp1, Fp2, Fm0, Fm1, Fm2, Gp0, Gp1, Gp2, Gm0, Gm1, Gm2;
+      flux_x(A0 + B0 * is3, A1 + B1 * is3, A2 + B2 * is3, g, tol, Fp0, Fp1, Fp2);
+      flux_x(A0 - B0 * is3, A1 - B1 * is3, A2 - B2 * is3, g, tol, Fm0, Fm1, Fm2);
+      flux_y(C0 + D0 * is3, C1 + D1 * is3, C2 + D2 * is3, g, tol, Gp0, Gp1, Gp2);
+      flux_y(C0 - D0 * is3, C1 - D1 * is3, C2 - D2 * is3, g, tol, Gm0, Gm1, Gm2);
+      // operators, Eq. (4)
+      real Lop[9];
+      const real idx = s.idx, idy = s.idy;
+      const real m3x = real(-3) * idx, m3y = real(-3) * idy;
+      Lop[0] = -(FE0 - FW0) * idx - (GN0 - GS0) * idy;
+      Lop[3] = -(FE1 - FW1) * idx - (GN1 - GS1) * idy - two_g * A0 * zbx * idx;
+      Lop[6] = -(FE2 - FW2) * idx - (GN2 - GS2) * idy - two_g * C0 * zby * idy;
+      Lop[1] = m3x * ((FE0 + FW0) - (Fp0 + Fm0));
+      Lop[4] = m3x * ((FE1 + FW1) - (Fp1 + Fm1) + tg3 * B0 * zbx);
+      Lop[7] = m3x * ((FE2 + FW2) - (Fp2 + Fm2));
+      Lop[2] = m3y * ((GN0 + GS0) - (Gp0 + Gm0));
+      Lop[5] = m3y * ((GN1 + GS1) - (Gp1 + Gm1));
+      Lop[8] = m3y * ((GN2 + GS2) - (Gp2 + Gm2) + tg3 * D0 * zby);
+
+      real o[9];
+      if (STAGE == 1) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) o[k] = cur.W[k] + dt * Lop[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) o[k] = half * (W1[k] + cur.W[k] + dt * Lop[k]);
+      }
+      if (!(o[0] > tol)) {
+#pragma unroll
+        for (int k = 3; k < 9; ++k) o[k] = real(0);
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) dst[k * s.P + cidx] = o[k];
+
+      if (STAGE == 2) {
+        const double m = cfl_candidate(o[0], o[3], o[6], g, tol, s.dx, s.dy);
+        mloc = m < mloc ? m : mloc;
+        if (o[0] != o[0]) flags |= kFlagNaN;
+        if (o[0] < real(-1e-6)) flags |= kFlagNegative;
+        if (gmask) {
+          for (int k = 0; k < s.ng; ++k) {
+            if (!((gmask >> k) & 1ull)) continue;
+            if (s.g_cell[k] != (int)cidx) continue;
+            const real xi = s.g_xi[k], ze = s.g_zeta[k];
+            const real h = o[0] + xi * o[1] + ze * o[2];
+            const real qx = o[3] + xi * o[4] + ze * o[5];
+            const real qy = o[6] + xi * o[7] + ze * o[8];
+            real *gb = s.g_buf + (gslot + k) * 4;
+            gb[0] = h;
+            gb[1] = h + s.g_z[k];
+            gb[2] = h > tol ? qx / h : real(0);
+            gb[3] = h > tol ? qy / h : real(0);
+          }
+        }
+      }
+    }
+
+    cur = nxt;
+    GS0 = GN0;
+    GS1 = GN1;
+    GS2 = GN2;
+    dS = dN;
+  }
+
+  if (STAGE == 2) {
+    const unsigned long long bits = wave_min_u64((unsigned long long)__double_as_longlong(mloc));
+    const unsigned long long anyflag = __ballot(flags != 0);
+    if (lane == 0 && bits != kInfBits) {
+      const unsigned long long seen =
+          __hip_atomic_load(&s.ctrl->minbits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (bits < seen) atomicMin(&s.ctrl->minbits, bits);
+    }
+    if (anyflag && flags) atomicOr(&s.ctrl->flags, flags);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step planner: one thread.  Finishes a step (t += dt, counters, gauge time),
+// takes the Courant minimum of the new state, and plans the next step size,
+// rain depth and stage inflows.
+// ---------------------------------------------------------------------------
+
+__device__ double hydrograph_at(int n, const double *t, const double *Q, double x) {
+  if (x <= t[0]) return Q[0];
+  if (x >= t[n - 1]) return Q[n - 1];
+  int k = 0;
+  while (k + 1 < n && t[k + 1] <= x) ++k;
+  const double w = (x - t[k]) / (t[k + 1] - t[k]);
+  return Q[k] * (1.0 - w) + Q[k + 1] * w;
+}
+
+__device__ void plan_next(Ctrl *c, const PlanArgs &p) {
+  const double t = c->t;
+  const double cand = p.fixed_dt > 0.0 ? p.fixed_dt : fmin(p.cfl * c->cflmin, p.dt_max);
+  double dt = fmin(cand, c->t_end - t);
+  if (!(dt > 0.0)) dt = 0.0;
+  c->dt = dt;
+  c->rain = p.rain_rate > 0.0 ? p.rain_rate * fmax(0.0, fmin(t + dt, p.rain_te) - fmax(t, p.rain_tb))
+                              : 0.0;
+  for (int sd = 0; sd < 4; ++sd) {
+    if (p.nhyd[sd] > 0) {
+      c->qin[sd][0] = hydrograph_at(p.nhyd[sd], p.hyd_t[sd], p.hyd_Q[sd], t) / p.seg_len[sd];
+      c->qin[sd][1] = hydrograph_at(p.nhyd[sd], p.hyd_t[sd], p.hyd_Q[sd], t + dt) / p.seg_len[sd];
+    } else {
+      c->qin[sd][0] = 0.0;
+      c->qin[sd][1] = 0.0;
+    }
+  }
+}
+
+__global__ void k_plan(Ctrl *c, PlanArgs p, int mode, double t_end, int set_tend) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (set_tend) c->t_end = t_end;
+  if (mode == kPlanFinishStep) {
+    const double dt = c->dt;
+    if (!(dt > 0.0)) return;  // the queued step was idle
+    const double t0 = c->t;
+    const double t1 = (dt == c->t_end - t0) ? c->t_end : t0 + dt;
+    c->t = t1;
+    c->last_dt = dt;
+    c->step += 1;
+    if (p.ng > 0) {
+      p.gauge_t[c->gauge_written % p.gauge_cap] = t1;
+      c->gauge_written += 1;
+    }
+    mode = kPlanFromMin;
+  }
+  if (mode == kPlanFromMin) {
+    c->cflmin = __longlong_as_double((long long)c->minbits);
+    c->minbits = kInfBits;
+  }
+  plan_next(c, p);
+}
+
+// Courant minimum of the current state (after the state was set from the host).
+template <typename real>
+__global__ void __launch_bounds__(256) k_cfl(Scen<real> s, Consts c) {
+  const long long n = (long long)s.nx * s.ny;
+  const real g = (real)c.g, tol = (real)c.tol;
+  double m = __longlong_as_double((long long)kInfBits);
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x) {
+    const double v = cfl_candidate(s.U[k], s.U[3 * s.P + k], s.U[6 * s.P + k], g, tol, s.dx, s.dy);
+    m = v < m ? v : m;
+  }
+  const unsigned long long bits = wave_min_u64((unsigned long long)__double_as_longlong(m));
+  if ((threadIdx.x & 63) == 0 && bits != kInfBits) atomicMin(&s.ctrl->minbits, bits);
+}
+
+// Diagnostics: per-block partial sums (mass, energy, min depth, NaN count),
+// then one block reduces the partials in a fixed order.
+template <typename real>
+__global__ void __launch_bounds__(256) k_diag(Scen<real> s, Consts c, double *part) {
+  __shared__ double sh[4][256];
+  const long long n = (long long)s.nx * s.ny;
+  const double g = c.g, tol = c.tol;
+  double mass = 0.0, en = 0.0, mn = __longlong_as_double((long long)kInfBits), nan = 0.0;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x) {
+    const double h0 = s.U[k];
+    mass += h0;
+    mn = h0 < mn ? h0 : mn;
+    if (h0 != h0) nan += 1.0;
+    double e = 0.0;
+    for (int a = -1; a <= 1; a += 2) {
+      for (int b = -1; b <= 1; b += 2) {
+        const double xa = a * kInvSqrt3, yb = b * kInvSqrt3;
+        const double h = h0 + xa * (double)s.U[s.P + k] + yb * (double)s.U[2 * s.P + k];
+        const double qx = (double)s.U[3 * s.P + k] + xa * (double)s.U[4 * s.P + k] +
+                          yb * (double)s.U[5 * s.P + k];
+        const double qy = (double)s.U[6 * s.P + k] + xa * (double)s.U[7 * s.P + k] +
+                          yb * (double)s.U[8 * s.P + k];
+        const double z = (double)s.z[k] + xa * (double)s.z[s.P + k] + yb * (double)s.z[2 * s.P + k];
+        const double kin = h > tol ? 0.5 * (qx * qx + qy * qy) / h : 0.0;
+        e += kin + 0.5 * g * ((h + z) * (h + z) - z * z);
+      }
+    }
+    en += e;
+  }
+  const int t = threadIdx.x;
+  sh[0][t] = mass;
+  sh[1][t] = en;
+  sh[2][t] = mn;
+  sh[3][t] = nan;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (t < w) {
+      sh[0][t] += sh[0][t + w];
+      sh[1][t] += sh[1][t + w];
+      sh[2][t] = fmin(sh[2][t], sh[2][t + w]);
+      sh[3][t] += sh[3][t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[4 * blockIdx.x + 0] = sh[0][0];
+    part[4 * blockIdx.x + 1] = sh[1][0];
+    part[4 * blockIdx.x + 2] = sh[2][0];
+    part[4 * blockIdx.x + 3] = sh[3][0];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_diag_final(const double *part, int nb, double *out) {
+  __shared__ double sh[4][256];
+  const int t = threadIdx.x;
+  double a = 0.0, b = 0.0, m = __longlong_as_double((long long)kInfBits), d = 0.0;
+  for (int k = t; k < nb; k += 256) {
+    a += part[4 * k];
+    b += part[4 * k + 1];
+    m = fmin(m, part[4 * k + 2]);
+    d += part[4 * k + 3];
+  }
+  sh[0][t] = a;
+  sh[1][t] = b;
+  sh[2][t] = m;
+  sh[3][t] = d;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (t < w) {
+      sh[0][t] += sh[0][t + w];
+      sh[1][t] += sh[1][t + w];
+      sh[2][t] = fmin(sh[2][t], sh[2][t + w]);
+      sh[3][t] += sh[3][t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = sh[0][0];
+    out[1] = sh[1][0];
+    out[2] = sh[2][0];
+    out[3] = sh[3][0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+Launch make_launch(int nx, int ny, int variant, int R, int wpb) {
+  Launch L;
+  const int cols = variant == 1 ? kStripLL : kStripNL;
+  L.nstrips = (nx + cols - 1) / cols;
+  if (R <= 0) {
+    long long r = (long long)L.nstrips * ny / 2048;
+    R = (int)(r < 8 ? 8 : (r > 64 ? 64 : r));
+  }
+  if (R > ny) R = ny;
+  L.R = R;
+  L.wpb = (wpb == 1 || wpb == 2 || wpb == 4) ? wpb : 4;
+  L.nitems = L.nstrips * ((ny + R - 1) / R);
+  return L;
+}
+
+template <typename real>
+hipError_t launch_stage(int stage, int variant, const Scen<real> &s, const Consts &c,
+                        const Launch &L, hipStream_t st) {
+  if (variant != 0) return hipErrorNotSupported;
+  const dim3 block(64 * L.wpb);
+  const dim3 grid((L.nitems + L.wpb - 1) / L.wpb);
+  if (stage == 1)
+    hipLaunchKernelGGL((k_stage_nl<real, 1>), grid, block, 0, st, s, c, L);
+  else
+    hipLaunchKernelGGL((k_stage_nl<real, 2>), grid, block, 0, st, s, c, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan(Ctrl *ctrl, const PlanArgs &p, int mode, double t_end, int set_tend,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, st, ctrl, p, mode, t_end, set_tend);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_cfl(const Scen<real> &s, const Consts &c, hipStream_t st) {
+  const long long n = (long long)s.nx * s.ny;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((k_cfl<real>), dim3((unsigned)blocks), dim3(256), 0, st, s, c);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_diag(const Scen<real> &s, const Consts &c, double *partials, int nblocks,
+                       double *out4, hipStream_t st) {
+  hipLaunchKernelGGL((k_diag<real>), dim3(nblocks), dim3(256), 0, st, s, c, partials);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, st, partials, nblocks, out4);
+  return hipGetLastError();
+}
+
+template hipError_t launch_stage<double>(int, int, const Scen<double> &, const Consts &,
+                                         const Launch &, hipStream_t);
+template hipError_t launch_stage<float>(int, int, const Scen<float> &, const Consts &,
+                                        const Launch &, hipStream_t);
+template hipError_t launch_cfl<double>(const Scen<double> &, const Consts &, hipStream_t);
+template hipError_t launch_cfl<float>(const Scen<float> &, const Consts &, hipStream_t);
+template hipError_t launch_diag<double>(const Scen<double> &, const Consts &, double *, int,
+                                        double *, hipStream_t);
+template hipError_t launch_diag<float>(const Scen<float> &, const Consts &, double *, int,
+                                       double *, hipStream_t);
+
+}  // namespace dg2

@@ -1,0 +1,193 @@
+"""GPU parity: the HIP DG2 step (through the C ABI) against the FP64 CPU oracle.
+
+Every comparison is element by element on the same seeded inputs.  FP64
+tolerances are set from rounding (the kernels use reciprocal multiplies,
+fused multiply-adds and rcbrt where the oracle divides and calls pow), far
+below the 1e-10 m bar on depth.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import dg2_oracle as O
+from paper_2010_02003_amd import dg2
+from paper_2010_02003_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _assert_close(gpu, ref, rtol, what):
+    gpu = np.asarray(gpu)
+    ref = np.asarray(ref)
+    scale = np.maximum(np.abs(ref).reshape(ref.shape[0], -1).max(axis=1), 1.0)
+    err = np.abs(gpu - ref).reshape(ref.shape[0], -1).max(axis=1) / scale
+    assert np.all(np.isfinite(gpu)), what
+    assert err.max() <= rtol, "%s: plane errors %s" % (what, err)
+    return err.max()
+
+
+def _sim(nx, ny, dx, dy, Z, manning, precision="fp64", variant="NL", **kw):
+    s = dg2.Sim(nx, ny, dx, dy, precision=precision, variant=variant, **kw)
+    s.set_dem_corners(Z)
+    s.set_manning(manning)
+    return s
+
+
+@pytest.mark.parametrize("nx,ny", [(70, 45), (133, 7), (1, 5), (6, 1), (62, 62), (125, 64)])
+def test_one_step_random_wet_dry_state(nx, ny):
+    _say("one step on random wet/dry modes", nx, ny)
+    modes, Z = WL.random_modes(nx, ny, seed=nx * 1000 + ny, slope=1.2)
+    rng = np.random.default_rng(nx + ny)
+    man = rng.uniform(0.0, 0.06, size=(ny, nx))
+    dx, dy, dt = 2.0, 0.5, 2e-3
+    s = _sim(nx, ny, dx, dy, Z, man)
+    s.set_state(modes, 0.0)
+    s.set_fixed_dt(dt)
+    s.step(1)
+    gpu, t, step, ldt = s.get_state()
+    prm = O.Params(nx=nx, ny=ny, dx=dx, dy=dy, manning=O._t(man), fixed_dt=dt)
+    ref = O.step(O.from_planes(modes), 0.0, O.bed_from_corners(Z), prm, dt)
+    assert step == 1 and ldt == dt and t == dt
+    _assert_close(gpu, O.to_planes(ref), 1e-12, "one step")
+
+
+def test_one_step_with_inflow_on_every_side_and_rain():
+    nx, ny, dx = 37, 29, 2.0
+    _say("inflow on four sides + rain", nx, ny)
+    modes, Z = WL.random_modes(nx, ny, seed=5, slope=0.8, wet_fraction=0.6)
+    s = _sim(nx, ny, dx, dx, Z, 0.03)
+    segs = {O.WEST: (3, 11), O.EAST: (20, 28), O.SOUTH: (0, 36), O.NORTH: (5, 5)}
+    hyd = {O.WEST: ([0.0, 5.0], [2.0, 6.0]), O.EAST: ([0.0, 1.0, 9.0], [0.5, 1.5, 0.0]),
+           O.SOUTH: ([0.0], [3.0]), O.NORTH: ([-1.0, 20.0], [0.2, 0.2])}
+    infl = []
+    for side, (a, b) in segs.items():
+        s.set_boundary(side, dg2.BC_INFLOW_Q, a, b)
+        s.set_inflow_hydrograph(side, *hyd[side])
+        infl.append(O.InflowBC(side, a, b, O._t(hyd[side][0]), O._t(hyd[side][1])))
+    s.set_rainfall(1e-3, 0.5, 4.0)
+    s.set_state(modes, 0.7)
+    s.set_fixed_dt(0.01)
+    s.step(3)
+    gpu, t, step, _ = s.get_state()
+    prm = O.Params(nx=nx, ny=ny, dx=dx, dy=dx, manning=0.03, inflows=infl, rain=(1e-3, 0.5, 4.0),
+                   fixed_dt=0.01)
+    r = O.run(O.from_planes(modes), O.bed_from_corners(Z), prm, steps=3, t0=0.7)
+    assert step == 3 and abs(t - r.t) < 1e-14
+    _assert_close(gpu, O.to_planes(r.U), 1e-12, "inflow + rain")
+
+
+def test_dam_break_bump_500_steps_fp64_matches_oracle_to_1e10():
+    sc = WL.dambreak_bump()
+    _say("dam break over bump 128x128 FP64 DG2-NL, 500 steps")
+    s = dg2.sim_from_scenario(sc)
+    s.step(sc.steps)
+    gpu, t, step, _ = s.get_state()
+    U, bed, prm = O.setup(sc)
+    r = O.run(U, bed, prm, steps=sc.steps)
+    ref = O.to_planes(r.U)
+    dh = np.abs(gpu[:3] - ref[:3]).max()
+    _say("max |dh| over the h modes = %.3e, t gpu %.15f oracle %.15f" % (dh, t, r.t))
+    assert step == sc.steps
+    assert dh <= 1e-10
+    assert abs(t - r.t) <= 1e-12 * r.t
+    _assert_close(gpu, ref, 1e-10, "dam break")
+
+
+def test_run_to_lands_on_T_and_gauges_match():
+    sc = WL.dambreak_bump(nx=48, ny=40)
+    gauges = np.array([[10.3, 20.2], [30.0, 11.5], [47.9, 39.9], [0.1, 0.1]])
+    _say("run_to 3.0 s with 4 gauges, 48x40")
+    s = dg2.sim_from_scenario(sc)
+    s.set_gauges(gauges)
+    s.run_to(3.0)
+    gpu, t, step, _ = s.get_state()
+    samples, gt = s.read_gauges()
+    U, bed, prm = O.setup(sc)
+    r = O.run(U, bed, prm, t_end=3.0, gauges=gauges)
+    assert t == 3.0 and r.t == 3.0
+    assert step == r.steps
+    assert samples.shape == (r.steps, 4, 4)
+    np.testing.assert_allclose(gt, np.array(r.gauge_t), rtol=1e-13, atol=0)
+    ref = np.stack([g.numpy() for g in r.gauges])
+    np.testing.assert_allclose(samples, ref, rtol=1e-11, atol=1e-12)
+    # a second run_to continues from T
+    s.run_to(3.5)
+    assert s.time()[0] == 3.5
+
+
+def test_launch_shape_does_not_change_results():
+    sc = WL.dambreak_bump(nx=150, ny=70)
+    outs = []
+    for rows, wpb in ((1, 4), (3, 1), (8, 2), (64, 4), (0, 4)):
+        _say("launch shape rows=%d waves=%d" % (rows, wpb))
+        s = dg2.sim_from_scenario(sc)
+        s.set_launch(rows, wpb)
+        s.step(30)
+        outs.append(s.get_state()[0])
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_mass_is_conserved_on_device_with_walls():
+    sc = WL.dambreak_bump(nx=96, ny=80)
+    s = dg2.sim_from_scenario(sc)
+    m0, e0, _ = s.diagnostics()
+    U, bed, prm = O.setup(sc)
+    assert abs(m0 - O.mass(U, prm)) <= 1e-13 * m0
+    assert abs(e0 - O.energy(U, bed, prm)) <= 1e-12 * abs(e0)
+    s.step(400)
+    m1, e1, hmin = s.diagnostics()
+    _say("mass drift %.3e, energy ratio %.6f, min h %.4f" % ((m1 - m0) / m0, e1 / e0, hmin))
+    assert abs(m1 - m0) <= 2e-13 * m0
+    assert e1 < e0  # numerical dissipation only removes energy
+    assert hmin > 0
+
+
+def test_fp32_depth_error_against_fp64_oracle():
+    """FP32 state and arithmetic: stated depth error after the 500-step dam break."""
+    sc = WL.dambreak_bump()
+    s = dg2.sim_from_scenario(sc, precision="fp32")
+    s.step(sc.steps)
+    gpu, t, step, _ = s.get_state()
+    U, bed, prm = O.setup(sc)
+    r = O.run(U, bed, prm, steps=sc.steps)
+    ref = O.to_planes(r.U)
+    dh = np.abs(gpu[0] - ref[0]).max()
+    _say("FP32 vs FP64 oracle: max |dh0| = %.3e m, t %.6f vs %.6f" % (dh, t, r.t))
+    assert dh <= 2e-4
+    assert abs(t - r.t) <= 1e-5 * r.t
+
+
+def test_invalid_inputs_are_rejected():
+    s = dg2.Sim(8, 6, 1.0)
+    bad = np.zeros((9, 6, 8))
+    bad[0, 2, 3] = -1.0
+    with pytest.raises(dg2.DG2Error) as e:
+        s.set_state(bad)
+    assert e.value.status == -1
+    bad[0, 2, 3] = np.nan
+    with pytest.raises(dg2.DG2Error):
+        s.set_state(bad)
+    with pytest.raises(dg2.DG2Error):
+        s.set_manning(-0.1)
+    with pytest.raises(dg2.DG2Error):
+        s.set_boundary(dg2.WEST, dg2.BC_INFLOW_Q, 3, 9)
+    with pytest.raises(dg2.DG2Error):
+        s.set_inflow_hydrograph(dg2.WEST, [0.0, 0.0], [1.0, 1.0])
+    with pytest.raises(dg2.DG2Error):
+        s.set_gauges([[100.0, 1.0]])
+    with pytest.raises(dg2.DG2Error):
+        dg2.Sim(0, 5, 1.0)
+
+
+def test_dry_domain_takes_dt_max_and_stays_dry():
+    s = dg2.Sim(20, 10, 1.0, dt_max=0.7)
+    s.step(5)
+    m, t, step, ldt = s.get_state()
+    assert step == 5 and ldt == 0.7 and abs(t - 3.5) < 1e-15
+    assert np.all(m == 0)
