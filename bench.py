@@ -1,0 +1,174 @@
+"""Benchmark of the DG2 time step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload urban|floodplain|dambreak]
+
+Default workload: the urban-like domain, 4096 x 4096 cells, dx = 0.5 m, from
+dry under 50 mm/h rain, Manning 0.02 on streets and 0.05 elsewhere, FP32,
+DG2-NL, 2000 steps: the configuration whose working set (>1 GB) exceeds the
+256 MB Infinity Cache, so that its bandwidth is HBM bandwidth.
+
+One step is one DG2 time step (two RK stages plus the device-side step
+planner).  The timed region runs exactly K steps from the initial condition
+with HIP events around every stage kernel on the library's stream.
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DG2 element-stage updates/s + % HBM peak; batched & adjoint vs plain"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("dg2_device.h", "dg2_kernels.hip", "dg2_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2010_02003_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(sc, esz):
+    """Bytes each stage kernel must move per cell: every plane read or written once.
+
+    stage 1 reads 9 state planes, 2 bed-slope planes and the Manning plane and
+    writes 9; stage 2 reads 9 stage-1 planes, 9 state planes, 2 bed slopes and
+    the Manning plane and writes 9.  A uniform Manning value drops its plane.
+    """
+    nplane = 1 if isinstance(sc.manning, np.ndarray) else 0
+    s1 = (9 + 2 + nplane + 9) * esz
+    s2 = (9 + 9 + 2 + nplane + 9) * esz
+    return s1, s2
+
+
+def make_workload(name):
+    from paper_2010_02003_amd import workloads as WL
+
+    if name == "urban":
+        return WL.urban()
+    if name == "floodplain":
+        return WL.floodplain()
+    if name == "dambreak":
+        return WL.dambreak_bump()
+    raise SystemExit("unknown workload " + name)
+
+
+def cpu_baseline(sc, budget_s=15.0):
+    """The FP64 oracle, as it stands, on a corner window of the same workload."""
+    import torch
+
+    from oracle import dg2_oracle as O
+
+    w = min(512, sc.nx, sc.ny)
+    sub = sc.__class__(**{**sc.__dict__})
+    sub.nx = sub.ny = w
+    sub.Z = sc.Z[: w + 1, : w + 1]
+    sub.surface = sc.surface[: w + 1, : w + 1]
+    if isinstance(sc.manning, np.ndarray):
+        sub.manning = sc.manning[:w, :w]
+    sub.inflows = [b for b in sc.inflows if (b.last < w)]
+    U, bed, prm = O.setup(sub)
+    t0 = time.perf_counter()
+    r = O.run(U, bed, prm, steps=1)
+    one = time.perf_counter() - t0
+    steps = int(max(1, min(400, budget_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    O.run(r.U, bed, prm, steps=steps, t0=r.t)
+    el = time.perf_counter() - t0
+    rate = w * w * 2 * steps / el
+    return {"value": rate, "unit": "element-stage updates/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": "%dx%d corner window of the %s workload, FP64 torch-CPU oracle, %d steps "
+                      "after one warm-up step" % (w, w, sc.name, steps)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="urban")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rows", type=int, default=0, help="rows per wavefront (0: built-in)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the DG2 step here runs on a single MI355X "
+              "(multi-GPU sharding is described in DESIGN.md, not built); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2010_02003_amd import dg2
+
+    assert torch.cuda.is_available(), "bench.py needs the MI355X"
+    torch.cuda.set_device(0)
+    sc = make_workload(args.workload)
+    esz = 4 if sc.precision == "fp32" else 8
+    sim = dg2.sim_from_scenario(sc, stream="torch")
+    if args.rows:
+        sim.set_launch(args.rows, 4)
+    # warm-up: real steps, then back to the initial condition
+    if args.warmup > 0:
+        sim.step(args.warmup)
+        sim.sync()
+    sim.set_initial_corners(sc.surface, sc.is_eta, sc.qx, sc.qy)
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    ms1, ms2, ms_step_ev = sim.time_kernels(args.steps)  # K steps, HIP events per kernel
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_sim, nstep, last_dt = sim.time()
+    mass, energy, hmin = sim.diagnostics()
+
+    cells = sc.nx * sc.ny
+    value = cells * 2 * args.steps / wall
+    b1, b2 = algorithmic_bytes(sc, esz)
+    ach2 = cells * b2 / (ms2 * 1e-3) / 1e9
+    ach1 = cells * b1 / (ms1 * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        tj = json.load(open(tfile))
+        ent = tj.get(args.workload)
+        if ent and ent.get("kernel_hash") == kernel_source_hash():
+            traffic = ent.get("stage2_bytes_per_launch")
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "element-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if esz == 4 else "f64",
+        "data": "synthetic",
+        "config": {"workload": sc.name, "nx": sc.nx, "ny": sc.ny, "dx": sc.dx, "variant": "DG2-" + sc.variant,
+                   "precision": sc.precision, "cells": cells, "sim_time_s": t_sim,
+                   "last_dt_s": last_dt, "mass_m3": mass, "min_h0": hmin},
+        "roofline": {"bound": "hbm", "kernel": "stage 2 (k_stage_nl<%s,2>)" % ("float" if esz == 4 else "double"),
+                     "achieved": ach2, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach2 / HBM_PEAK_GBS,
+                     "traffic": traffic, "bytes_per_cell": b2, "ms_per_launch": ms2,
+                     "stage1": {"achieved": ach1, "frac": ach1 / HBM_PEAK_GBS, "bytes_per_cell": b1,
+                                "ms_per_launch": ms1},
+                     "step_frac": cells * (b1 + b2) / (wall / args.steps) / 1e9 / HBM_PEAK_GBS},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -35,8 +35,9 @@ library implements):
   * time step: Cr * min over wet cell means of min(dx/(|u|+c), dy/(|v|+c)),
     capped by dt_max and by the time left to the target;
   * RK2 is the SSP (Heun) average U^{n+1} = (W + U1 + dt L(U1)) / 2;
-  * friction: linearised-implicit point update, once per time step with the
-    full dt, increments added to the discharge modes;
+  * friction: implicit (exact) integral of the split friction ODE at frozen
+    depth at the centre and the four Gauss points, once per time step with
+    the full dt, increments added to the discharge modes;
   * walls: mirror ghost cells; discharge inflow: prescribed face flux;
     rainfall: added to the mean depth mode before friction;
   * cells whose mean depth is at or below the drying tolerance get zero
@@ -368,28 +369,24 @@ def spatial_operator(W: torch.Tensor, bed: Bed, prm: Params, t_stage: float) -> 
 # ---------------------------------------------------------------------------
 
 def friction_increment(h, qx, qy, n, dt, g, tol):
-    """Linearised-implicit friction increment of the discharges at one point.
+    """Implicit friction increment of the discharges at one point.
 
-    S_f = -C_f u|V| (x) and -C_f v|V| (y) with C_f = g n^2 h^(-1/3) (Eq. 1);
-    q_new = q + dt S_f / (1 - dt dS_f/dq), skipped where the point is dry,
-    motionless or frictionless.
+    The split friction ODE dq/dt = S_f = -C_f |V| q / h (Eq. 1, C_f = g n^2
+    h^(-1/3), V the velocity) keeps the depth and the flow direction fixed,
+    so over a step dt its implicit solution is exact:
+    q_new = q / (1 + dt C_f |V| / h).  Returns q_new - q; zero where the
+    point is dry, motionless or frictionless.
     """
     n = _t(n) if not torch.is_tensor(n) else n
     qq = qx * qx + qy * qy
     active = (h > tol) & (qq > 0.0) & (n > 0.0)
     hs = torch.where(active, h, torch.ones_like(h))
-    qs = torch.where(active, qq, torch.ones_like(h))
-    u = qx / hs
-    v = qy / hs
-    V = torch.sqrt(qs) / hs
+    V = torch.sqrt(torch.where(active, qq, torch.ones_like(h))) / hs
     Cf = g * n * n * torch.pow(hs, -1.0 / 3.0)
-    Sx = -Cf * u * V
-    Sy = -Cf * v * V
-    Dx = -Cf * (2.0 * u * u + v * v) / (hs * V)
-    Dy = -Cf * (u * u + 2.0 * v * v) / (hs * V)
+    factor = 1.0 / (1.0 + dt * Cf * V / hs)
     zero = torch.zeros_like(h)
-    return (torch.where(active, dt * Sx / (1.0 - dt * Dx), zero),
-            torch.where(active, dt * Sy / (1.0 - dt * Dy), zero))
+    return (torch.where(active, qx * factor - qx, zero),
+            torch.where(active, qy * factor - qy, zero))
 
 
 def apply_friction(W: torch.Tensor, n, dt: float, g: float, tol: float) -> torch.Tensor:
@@ -504,11 +501,29 @@ def rain_depth(prm: Params, t: float, dt: float) -> float:
     return rate * max(0.0, min(t + dt, te) - max(t, tb))
 
 
-def zero_dry_discharge(U: torch.Tensor, tol: float) -> torch.Tensor:
-    dry = U[H, M0] <= tol
+def wet_dry_fix(U: torch.Tensor, tol: float) -> torch.Tensor:
+    """End-of-stage wet/dry treatment of the element modes.
+
+    Dry elements (mean depth at or below tol, Sec. 2.1.3) get zero discharge
+    modes.  Partly wet elements (wet mean but a face-limit depth at or below
+    tol) drop every slope mode: they are locally first order at the front,
+    which keeps wedge-shaped planar depths holding almost no water from
+    carrying fictitious momentum.  Mean depths are never changed, so mass is
+    conserved exactly.
+    """
+    h0 = U[H, M0]
+    dry = h0 <= tol
+    lim = torch.minimum(torch.minimum(h0 + U[H, MX], h0 - U[H, MX]),
+                        torch.minimum(h0 + U[H, MY], h0 - U[H, MY]))
+    part = (~dry) & (lim <= tol)
     out = U.clone()
-    out[QX] = torch.where(dry, torch.zeros_like(U[QX]), U[QX])
-    out[QY] = torch.where(dry, torch.zeros_like(U[QY]), U[QY])
+    zero = torch.zeros_like(h0)
+    for var in (QX, QY):
+        for m in (M0, MX, MY):
+            out[var, m] = torch.where(dry, zero, U[var, m])
+    for var in (H, QX, QY):
+        for m in (MX, MY):
+            out[var, m] = torch.where(part, zero, out[var, m])
     return out
 
 
@@ -519,11 +534,11 @@ def step(U: torch.Tensor, t: float, bed: Bed, prm: Params, dt: float):
     W = apply_friction(W, prm.manning, dt, prm.g, prm.tol)
     if prm.variant == "LL":
         W = local_limit(W, bed, prm)
-    U1 = zero_dry_discharge(W + dt * spatial_operator(W, bed, prm, t), prm.tol)
+    U1 = wet_dry_fix(W + dt * spatial_operator(W, bed, prm, t), prm.tol)
     if prm.variant == "LL":
         U1 = local_limit(U1, bed, prm)
     U2 = 0.5 * (W + U1 + dt * spatial_operator(U1, bed, prm, t + dt))
-    return zero_dry_discharge(U2, prm.tol)
+    return wet_dry_fix(U2, prm.tol)
 
 
 # ---------------------------------------------------------------------------

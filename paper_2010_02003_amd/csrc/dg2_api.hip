@@ -245,10 +245,7 @@ dg2_status read_ctrl(dg2_ctx *c) {
 }
 
 dg2_status latched(dg2_ctx *c) {
-  if (c->hctrl->flags) {
-    return fail(c, DG2_ENUMERIC,
-                (c->hctrl->flags & kFlagNaN) ? "NaN in the state" : "negative mean depth below -1e-6 m");
-  }
+  if (c->hctrl->flags & kFlagNaN) return fail(c, DG2_ENUMERIC, "NaN in the state");
   return DG2_OK;
 }
 
@@ -626,7 +623,7 @@ dg2_status dg2_run_to(dg2_ctx *c, double T) {
       st = hipfail(c, e, "run_to");
       break;
     }
-    if (snap->flags) {
+    if (snap->flags & kFlagNaN) {
       st = latched(c);
       break;
     }

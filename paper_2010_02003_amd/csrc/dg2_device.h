@@ -158,9 +158,10 @@ __device__ __forceinline__ void flux_y(real h, real qx, real qy, real g, real to
   }
 }
 
-// Linearised-implicit friction increment at one point: with
-// b = dt g n^2 h^(-7/3),  dq_x = -b q_x |q|^2 / (|q| + b (2 q_x^2 + q_y^2)),
-// which equals dt S_f/(1 - dt dS_f/dq) for S_f = -C_f u|V|, C_f = g n^2 h^(-1/3).
+// Implicit friction increment at one point.  The split friction ODE
+// dq/dt = -C_f |V| q / h (C_f = g n^2 h^(-1/3)) keeps h and the flow direction,
+// so its implicit solution over dt is exact: q_new = q / (1 + b |q|) with
+// b = dt g n^2 h^(-7/3).  gn2dt = g n^2 dt.
 template <typename real>
 __device__ __forceinline__ void friction_point(real h, real qx, real qy, real gn2dt, real tol,
                                                real &dqx, real &dqy) {
@@ -169,10 +170,10 @@ __device__ __forceinline__ void friction_point(real h, real qx, real qy, real gn
     const real rc = drcbrt(h);
     const real rc2 = rc * rc;
     const real b = gn2dt * (rc2 * rc2) * (rc2 * rc);
-    const real qm = dsqrt(qq);
-    const real bq = b * qq;
-    dqx = -bq * qx / (qm + b * (real(2) * qx * qx + qy * qy));
-    dqy = -bq * qy / (qm + b * (qx * qx + real(2) * qy * qy));
+    const real bq = b * dsqrt(qq);
+    const real f = bq / (real(1) + bq);
+    dqx = -qx * f;
+    dqy = -qy * f;
   } else {
     dqx = real(0);
     dqy = real(0);
@@ -216,6 +217,22 @@ __device__ __forceinline__ void mirror(real *W, bool mx, bool my) {
     W[5] = -W[5];
     W[6] = -W[6];
     W[7] = -W[7];
+  }
+}
+
+// End-of-stage wet/dry treatment: a dry element (mean depth <= tol) gets
+// zero discharge modes; a wet element with a face-limit depth <= tol drops
+// every slope mode (locally first order at the front).  Mean depths stay.
+template <typename real>
+__device__ __forceinline__ void wet_dry_fix(real *o, real tol) {
+  if (!(o[0] > tol)) {
+#pragma unroll
+    for (int k = 3; k < 9; ++k) o[k] = real(0);
+    return;
+  }
+  const real ax = fabs(o[1]), ay = fabs(o[2]);
+  if (o[0] - (ax > ay ? ax : ay) <= tol) {
+    o[1] = o[2] = o[4] = o[5] = o[7] = o[8] = real(0);
   }
 }
 

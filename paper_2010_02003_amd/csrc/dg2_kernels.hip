@@ -221,10 +221,7 @@ __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch
 #pragma unroll
         for (int k = 0; k < 9; ++k) o[k] = half * (W1[k] + cur.W[k] + dt * Lop[k]);
       }
-      if (!(o[0] > tol)) {
-#pragma unroll
-        for (int k = 3; k < 9; ++k) o[k] = real(0);
-      }
+      wet_dry_fix(o, tol);
 #pragma unroll
       for (int k = 0; k < 9; ++k) dst[k * s.P + cidx] = o[k];
 

@@ -191,3 +191,24 @@ def test_dry_domain_takes_dt_max_and_stays_dry():
     m, t, step, ldt = s.get_state()
     assert step == 5 and ldt == 0.7 and abs(t - 3.5) < 1e-15
     assert np.all(m == 0)
+
+
+def test_from_dry_channel_filling_matches_oracle():
+    """Wetting front from an inflow into a dry fBm channel: exercises the dummy
+    limits, the z* revision, the front treatment and the inflow face."""
+    nx, ny, dx = 48, 40, 2.0
+    X, Y = WL.corner_xy(nx, ny, dx, dx)
+    Z = WL.fbm_surface((ny + 1, nx + 1), 0.7, 2.0, 21) - 1.0 * (np.abs(Y - 40.0) <= 6.0)
+    s = _sim(nx, ny, dx, dx, Z, 0.035, dt_max=0.1)
+    s.set_boundary(dg2.WEST, dg2.BC_INFLOW_Q, 17, 22)
+    s.set_inflow_hydrograph(dg2.WEST, [0.0, 30.0], [0.0, 4.0])
+    s.set_initial_corners(np.zeros_like(Z), False)
+    _say("channel filling from dry, run_to 20 s")
+    s.run_to(20.0)
+    gpu, t, step, _ = s.get_state()
+    infl = [O.InflowBC(O.WEST, 17, 22, O._t([0.0, 30.0]), O._t([0.0, 4.0]))]
+    prm = O.Params(nx=nx, ny=ny, dx=dx, dy=dx, manning=0.035, dt_max=0.1, inflows=infl)
+    r = O.run(O.initial_state(Z, np.zeros_like(Z), False), O.bed_from_corners(Z), prm, t_end=20.0)
+    _say("steps gpu %d oracle %d, max |dh0| %.3e" % (step, r.steps, np.abs(gpu[0] - r.U[0, 0].numpy()).max()))
+    assert t == 20.0 and step == r.steps
+    _assert_close(gpu, O.to_planes(r.U), 1e-10, "channel filling")
