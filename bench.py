@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--workload", default="urban")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rows", type=int, default=0, help="rows per wavefront (0: built-in)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the timed region, copy this many MiB three times with a plain "
+                         "device copy (reference reading for the HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the DG2 step here runs on a single MI355X "
@@ -165,6 +168,14 @@ def main():
                      "step_frac": cells * (b1 + b2) / (wall / args.steps) / 1e9 / HBM_PEAK_GBS},
         "cpu_baseline": None,
     }
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 4
+        a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_mib"] = args.copy_mib
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc)
     print(json.dumps(out), flush=True)

@@ -23,15 +23,15 @@ def flags():
             "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + flags() + srcs + ["-o", tmp]
+def build(verbose: bool = False, csrc: str = CSRC, out: str = LIB, extra=()) -> str:
+    srcs = [os.path.join(csrc, s) for s in SOURCES]
+    tmp = out + ".tmp"
+    cmd = [HIPCC] + flags() + ["-I", csrc] + list(extra) + srcs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

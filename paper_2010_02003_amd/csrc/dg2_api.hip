@@ -316,7 +316,9 @@ dg2_status dg2_create(const dg2_config *cfg, dg2_ctx **out) {
   *out = nullptr;
   if (!cfg) return fail(nullptr, DG2_EINVAL, "cfg is NULL");
   if (cfg->nx < 1 || cfg->ny < 1) return fail(nullptr, DG2_EINVAL, "nx and ny must be >= 1");
-  if ((long long)cfg->nx * cfg->ny > (1ll << 30)) return fail(nullptr, DG2_EINVAL, "grid too large");
+  // one plane must stay below 4 GiB (32-bit in-plane offsets in the kernels)
+  if ((long long)cfg->nx * cfg->ny * (cfg->prec == DG2_FP32 ? 4 : 8) >= (1ll << 32))
+    return fail(nullptr, DG2_EINVAL, "grid too large: nx*ny must be < 2^29 (FP64) or 2^30 (FP32)");
   if (!(cfg->dx > 0) || !(cfg->dy > 0) || !std::isfinite(cfg->dx) || !std::isfinite(cfg->dy))
     return fail(nullptr, DG2_EINVAL, "dx and dy must be positive");
   if (!(cfg->g > 0) || !(cfg->cfl > 0) || !(cfg->tol_dry > 0) || !(cfg->dt_max > 0) ||

@@ -47,15 +47,45 @@ struct PlanArgs {
   double *gauge_t;
 };
 
+// Arithmetic kernels by precision.  FP64 keeps correctly rounded division,
+// square root and rcbrt.  FP32 uses the hardware reciprocal, square root,
+// exp2 and log2 (about 1 ulp): every operand here is a normal number (depths
+// above the drying tolerance, positive wave-speed gaps), so no range scaling
+// is needed, and the FP32 path is held to a stated depth error instead of
+// bitwise agreement.
 template <typename real> __device__ __forceinline__ real dsqrt(real x);
 template <> __device__ __forceinline__ double dsqrt<double>(double x) { return sqrt(x); }
-template <> __device__ __forceinline__ float dsqrt<float>(float x) { return sqrtf(x); }
-template <typename real> __device__ __forceinline__ real drcbrt(real x);
-template <> __device__ __forceinline__ double drcbrt<double>(double x) { return rcbrt(x); }
-template <> __device__ __forceinline__ float drcbrt<float>(float x) { return rcbrtf(x); }
+template <> __device__ __forceinline__ float dsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <typename real> __device__ __forceinline__ real drcp(real x);
+template <> __device__ __forceinline__ double drcp<double>(double x) { return 1.0 / x; }
+template <> __device__ __forceinline__ float drcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <typename real> __device__ __forceinline__ real ddiv(real a, real b);
+template <> __device__ __forceinline__ double ddiv<double>(double a, double b) { return a / b; }
+template <> __device__ __forceinline__ float ddiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+// h^(-7/3) for a depth h above the drying tolerance
+template <typename real> __device__ __forceinline__ real pow_m7_3(real h);
+template <> __device__ __forceinline__ double pow_m7_3<double>(double h) {
+  const double rc = rcbrt(h), rc2 = rc * rc;
+  return (rc2 * rc2) * (rc2 * rc);
+}
+template <> __device__ __forceinline__ float pow_m7_3<float>(float h) {
+  return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(h) * (-7.0f / 3.0f));
+}
 template <typename real> __device__ __forceinline__ real dcbrt(real x);
 template <> __device__ __forceinline__ double dcbrt<double>(double x) { return cbrt(x); }
 template <> __device__ __forceinline__ float dcbrt<float>(float x) { return cbrtf(x); }
+
+// Element of a plane at a 32-bit byte offset: plane bases stay in scalar
+// registers and each lane supplies only its 32-bit offset (one plane is
+// below 4 GiB), which saves the 64-bit address arithmetic per access.
+template <typename real>
+__device__ __forceinline__ real ld_at(const real *plane, unsigned off) {
+  return *reinterpret_cast<const real *>(reinterpret_cast<const char *>(plane) + off);
+}
+template <typename real>
+__device__ __forceinline__ void st_at(real *plane, unsigned off, real v) {
+  *reinterpret_cast<real *>(reinterpret_cast<char *>(plane) + off) = v;
+}
 
 template <typename real> __device__ __forceinline__ real dmax(real a, real b) { return a > b ? a : b; }
 template <typename real> __device__ __forceinline__ real dmin(real a, real b) { return a < b ? a : b; }
@@ -67,7 +97,7 @@ __device__ __forceinline__ void dummy_limit(real h, real qx, real qy, real tol, 
                                             real &v) {
   hs = h > real(0) ? h : real(0);
   if (h > tol) {
-    const real r = real(1) / h;
+    const real r = drcp(h);
     u = qx * r;
     v = qy * r;
   } else {
@@ -100,7 +130,7 @@ __device__ __forceinline__ void hll(real hL, real uL, real vL, real hR, real uR,
   } else if (sR <= real(0)) {
     F0 = FR0; F1 = FR1; F2 = FR2;
   } else {
-    const real inv = real(1) / (sR - sL);
+    const real inv = drcp(sR - sL);
     const real ss = sL * sR;
     F0 = (sR * FL0 - sL * FR0 + ss * (hR - hL)) * inv;
     F1 = (sR * FL1 - sL * FR1 + ss * (qR - qL)) * inv;
@@ -115,7 +145,7 @@ __device__ __forceinline__ void inflow_flux(real q, real h_inner, real g, real &
   const real hc = dcbrt(q * q / g);
   const real hb = dmax(h_inner, hc);
   F0 = q;
-  F1 = q * q / hb + real(0.5) * g * hb * hb;
+  F1 = ddiv(q * q, hb) + real(0.5) * g * hb * hb;
 }
 
 // Physical x-flux at a point (Eq. 1), velocity zeroed at or below tol.
@@ -125,7 +155,7 @@ __device__ __forceinline__ void flux_x(real h, real qx, real qy, real g, real to
   const real hp = h > real(0) ? h : real(0);
   const real pres = real(0.5) * g * hp * hp;
   if (h > tol) {
-    const real r = real(1) / h;
+    const real r = drcp(h);
     const real u = qx * r, v = qy * r;
     const real q = hp * u;
     F0 = q;
@@ -145,7 +175,7 @@ __device__ __forceinline__ void flux_y(real h, real qx, real qy, real g, real to
   const real hp = h > real(0) ? h : real(0);
   const real pres = real(0.5) * g * hp * hp;
   if (h > tol) {
-    const real r = real(1) / h;
+    const real r = drcp(h);
     const real u = qx * r, v = qy * r;
     const real q = hp * v;
     G0 = q;
@@ -167,11 +197,9 @@ __device__ __forceinline__ void friction_point(real h, real qx, real qy, real gn
                                                real &dqx, real &dqy) {
   const real qq = qx * qx + qy * qy;
   if (h > tol && qq > real(0)) {
-    const real rc = drcbrt(h);
-    const real rc2 = rc * rc;
-    const real b = gn2dt * (rc2 * rc2) * (rc2 * rc);
+    const real b = gn2dt * pow_m7_3(h);
     const real bq = b * dsqrt(qq);
-    const real f = bq / (real(1) + bq);
+    const real f = ddiv(bq, real(1) + bq);
     dqx = -qx * f;
     dqy = -qy * f;
   } else {
@@ -241,9 +269,9 @@ template <typename real>
 __device__ __forceinline__ double cfl_candidate(real h0, real qx0, real qy0, real g, real tol,
                                                 real dx, real dy) {
   if (!(h0 > tol)) return __longlong_as_double((long long)kInfBits);
-  const real u = fabs(qx0 / h0), v = fabs(qy0 / h0);
+  const real u = fabs(ddiv(qx0, h0)), v = fabs(ddiv(qy0, h0));
   const real c = dsqrt(g * h0);
-  const real m = dmin(dx / (u + c), dy / (v + c));
+  const real m = dmin(ddiv(dx, u + c), ddiv(dy, v + c));
   return (double)m;
 }
 

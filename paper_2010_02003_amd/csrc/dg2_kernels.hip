@@ -55,27 +55,66 @@ __device__ __forceinline__ void y_face(const Row<real> &lo, const Row<real> &hi,
   G2 = fn;
 }
 
-// One row of the stage input at grid row r for the lane's column: loads the
-// 9 planes (clamped into the grid), mirrors ghosts, adds rain and applies
-// the friction split in stage 1, and forms the dummy face limits.
+// Raw planes of one row for the lane's column (clamped into the grid) and,
+// in stage 1, its Manning value.
 template <typename real, int STAGE>
-__device__ __forceinline__ void load_row(const Scen<real> &s, const real *src, int r, int ci,
-                                         bool mx, real rain, real gdt, real tol, Row<real> &row) {
+struct Raw {
+  real W[9];
+  real n;
+};
+
+template <typename real, int STAGE>
+__device__ __forceinline__ void load_raw(const Scen<real> &s, const real *src, int r, int ci,
+                                         Raw<real, STAGE> &raw) {
   const int rs = r < 0 ? 0 : (r >= s.ny ? s.ny - 1 : r);
-  const bool my = (r < 0) || (r >= s.ny);
-  const long long idx = (long long)rs * s.nx + ci;
+  const unsigned off = (unsigned)(rs * s.nx + ci) * (unsigned)sizeof(real);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) row.W[k] = src[k * s.P + idx];
-  real n = s.n_uniform;
-  if (STAGE == 1 && s.n) n = s.n[idx];
-  mirror(row.W, mx, my);
+  for (int k = 0; k < 9; ++k) raw.W[k] = ld_at(src + k * s.P, off);
+  if (STAGE == 1) raw.n = s.n ? ld_at(s.n, off) : s.n_uniform;
+}
+
+// Stage input of one row from its raw planes: mirror ghosts, then in stage 1
+// rain and the friction split, then the dummy face limits.
+template <typename real, int STAGE>
+__device__ __forceinline__ void build_row(const Raw<real, STAGE> &raw, int r, int ny, bool mx,
+                                          real rain, real gdt, real tol, Row<real> &row) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) row.W[k] = raw.W[k];
+  mirror(row.W, mx, (r < 0) || (r >= ny));
   if (STAGE == 1) {
     row.W[0] += rain;
-    apply_friction(row.W, gdt * n * n, tol);
+    apply_friction(row.W, gdt * raw.n * raw.n, tol);
   }
   row_limits(row, tol);
 }
 
+// Per-cell data of an output row: bed slopes and, in stage 2, the state U^n
+// and Manning value that rebuild the friction-split stage-1 input W1.
+template <typename real, int STAGE>
+struct Own {
+  real z1x, z1y;
+  real U[STAGE == 2 ? 9 : 1];
+  real n;
+};
+
+template <typename real, int STAGE>
+__device__ __forceinline__ void load_own(const Scen<real> &s, long long cidx, Own<real, STAGE> &o) {
+  const unsigned off = (unsigned)cidx * (unsigned)sizeof(real);
+  o.z1x = ld_at(s.z + s.P, off);
+  o.z1y = ld_at(s.z + 2 * s.P, off);
+  if (STAGE == 2) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) o.U[k] = ld_at(s.U + k * s.P, off);
+    o.n = s.n ? ld_at(s.n, off) : s.n_uniform;
+  }
+}
+
+// Software-pipelined march: the loads of row j+2 are issued at the top of
+// iteration j and consumed one iteration later, so they have a whole row of
+// arithmetic to hide behind; a row's own data (bed slopes and, in stage 2,
+// U^n and n) is loaded at the top of its iteration, ahead of the flux
+// arithmetic of that row.  Prefetching the own data a row earlier as well
+// costs more registers than it gains.
 template <typename real, int STAGE>
 __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch L) {
   const int lane = threadIdx.x & 63;
@@ -120,11 +159,16 @@ __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch
   }
 
   Row<real> cur, nxt;
+  Raw<real, STAGE> rawA, rawN;
+  Own<real, STAGE> ownC;
   real GS0, GS1, GS2, dS;
   {
     Row<real> prev;
-    load_row<real, STAGE>(s, src, j0 - 1, ci, mx, rain, gdt, tol, prev);
-    load_row<real, STAGE>(s, src, j0, ci, mx, rain, gdt, tol, cur);
+    load_raw<real, STAGE>(s, src, j0 - 1, ci, rawA);
+    load_raw<real, STAGE>(s, src, j0, ci, rawN);
+    build_row<real, STAGE>(rawA, j0 - 1, s.ny, mx, rain, gdt, tol, prev);
+    load_raw<real, STAGE>(s, src, j0 + 1, ci, rawA);
+    build_row<real, STAGE>(rawN, j0, s.ny, mx, rain, gdt, tol, cur);
     y_face(prev, cur, g, tol, GS0, GS1, GS2);
     dS = dmax(real(0), -prev.nr);
     if (j0 == 0 && colS) {
@@ -132,12 +176,17 @@ __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch
       GS1 = real(0);
     }
   }
+  // rawA holds row j0+1
 
   double mloc = __longlong_as_double((long long)kInfBits);
   unsigned flags = 0;
 
   for (int j = j0; j < j1; ++j) {
-    load_row<real, STAGE>(s, src, j + 1, ci, mx, rain, gdt, tol, nxt);
+    // prefetch: row j+2 and the own data of row j+1
+    if (j + 2 <= j1) load_raw<real, STAGE>(s, src, j + 2, ci, rawN);
+    if (own) load_own<real, STAGE>(s, (long long)j * s.nx + i, ownC);
+
+    build_row<real, STAGE>(rawA, j + 1, s.ny, mx, rain, gdt, tol, nxt);
 
     // north face of row j
     real GN0, GN1, GN2;
@@ -172,14 +221,12 @@ __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch
 
     if (own) {
       const long long cidx = (long long)j * s.nx + i;
-      const real z1x = s.z[s.P + cidx], z1y = s.z[2 * s.P + cidx];
       real W1[9];
       if (STAGE == 2) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) W1[k] = s.U[k * s.P + cidx];
-        const real n = s.n ? s.n[cidx] : s.n_uniform;
+        for (int k = 0; k < 9; ++k) W1[k] = ownC.U[k];
         W1[0] += rain;
-        apply_friction(W1, gdt * n * n, tol);
+        apply_friction(W1, gdt * ownC.n * ownC.n, tol);
       }
       // dummy modes, Eq. (5)
       const real e1 = cur.eh * cur.eu, e2 = cur.eh * cur.ev;
@@ -191,8 +238,8 @@ __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch
       const real C0 = half * (cur.nh + cur.sh), C1 = half * (n1 + s1), C2 = half * (n2 + s2);
       const real D0 = half * (cur.nh - cur.sh), D1 = half * (n1 - s1), D2 = half * (n2 - s2);
       // revised bed slopes: z*_face = z_face - max(0, -h^-) on each face
-      const real zbx = z1x - half * dE + half * dW;
-      const real zby = z1y - half * dN + half * dS;
+      const real zbx = ownC.z1x - half * dE + half * dW;
+      const real zby = ownC.z1y - half * dN + half * dS;
       // physical fluxes at the Gauss points
       real Fp0, Fp1, Fp2, Fm0, Fm1, Fm2, Gp0, Gp1, Gp2, Gm0, Gm1, Gm2;
       flux_x(A0 + B0 * is3, A1 + B1 * is3, A2 + B2 * is3, g, tol, Fp0, Fp1, Fp2);
@@ -222,14 +269,15 @@ __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch
         for (int k = 0; k < 9; ++k) o[k] = half * (W1[k] + cur.W[k] + dt * Lop[k]);
       }
       wet_dry_fix(o, tol);
+      const unsigned off = (unsigned)cidx * (unsigned)sizeof(real);
 #pragma unroll
-      for (int k = 0; k < 9; ++k) dst[k * s.P + cidx] = o[k];
+      for (int k = 0; k < 9; ++k) st_at(dst + k * s.P, off, o[k]);
 
       if (STAGE == 2) {
         const double m = cfl_candidate(o[0], o[3], o[6], g, tol, s.dx, s.dy);
         mloc = m < mloc ? m : mloc;
         if (o[0] != o[0]) flags |= kFlagNaN;
-        if (o[0] < real(-1e-6)) flags |= kFlagNegative;
+        if (o[0] < real(0)) flags |= kFlagNegative;
         if (gmask) {
           for (int k = 0; k < s.ng; ++k) {
             if (!((gmask >> k) & 1ull)) continue;
@@ -249,6 +297,7 @@ __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch
     }
 
     cur = nxt;
+    rawA = rawN;
     GS0 = GN0;
     GS1 = GN1;
     GS2 = GN2;
@@ -434,8 +483,10 @@ Launch make_launch(int nx, int ny, int variant, int R, int wpb) {
   const int cols = variant == 1 ? kStripLL : kStripNL;
   L.nstrips = (nx + cols - 1) / cols;
   if (R <= 0) {
-    long long r = (long long)L.nstrips * ny / 2048;
-    R = (int)(r < 8 ? 8 : (r > 64 ? 64 : r));
+    // aim at ~16k wavefronts: several rounds of the ~3-4k resident slots, so
+    // the last round is short, while the two halo rows stay a small share
+    long long r = (long long)L.nstrips * ny / 16384;
+    R = (int)(r < 4 ? 4 : (r > 32 ? 32 : r));
   }
   if (R > ny) R = ny;
   L.R = R;

@@ -20,7 +20,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdg2.so")
+LIB_PATH = os.environ.get("DG2_LIBRARY", os.path.join(_HERE, "libdg2.so"))
 
 FP64, FP32 = 0, 1
 NL, LL = 0, 1
