@@ -326,7 +326,6 @@ dg2_status dg2_create(const dg2_config *cfg, dg2_ctx **out) {
     return fail(nullptr, DG2_EINVAL, "g, cfl, tol_dry, dt_max must be > 0 and ll_threshold >= 0");
   if (cfg->prec != DG2_FP64 && cfg->prec != DG2_FP32) return fail(nullptr, DG2_EINVAL, "bad prec");
   if (cfg->variant != DG2_NL && cfg->variant != DG2_LL) return fail(nullptr, DG2_EINVAL, "bad variant");
-  if (cfg->variant == DG2_LL) return fail(nullptr, DG2_EUNSUPPORTED, "DG2-LL is not built yet");
 
   dg2_ctx *c = new (std::nothrow) dg2_ctx();
   if (!c) return fail(nullptr, DG2_ENOMEM, "host allocation failed");
@@ -354,6 +353,8 @@ dg2_status dg2_create(const dg2_config *cfg, dg2_ctx **out) {
   c->U = c->U_own;
   if ((s = alloc(c, &c->U1, 9 * pb, "stage buffer")) != DG2_OK) return bail(s);
   if ((s = alloc(c, &c->z, 3 * pb, "bed")) != DG2_OK) return bail(s);
+  if (cfg->variant == DG2_LL && (s = alloc(c, &c->W1, 9 * pb, "limited stage input")) != DG2_OK)
+    return bail(s);
   if ((s = alloc(c, (void **)&c->ctrl, sizeof(Ctrl), "ctrl")) != DG2_OK) return bail(s);
   if ((s = alloc(c, (void **)&c->diag_part, kDiagBlocks * 4 * sizeof(double), "diag")) != DG2_OK)
     return bail(s);

@@ -55,6 +55,142 @@ __device__ __forceinline__ void y_face(const Row<real> &lo, const Row<real> &hi,
   G2 = fn;
 }
 
+// DG2 operators of one element (Eq. 4) from its dummy face limits (carried
+// in the row record), the four face fluxes and the revised bed slopes
+// zbx = (z*_E - z*_W)/2, zby = (z*_N - z*_S)/2: dummy modes by Eq. (5),
+// physical fluxes at the Gauss points U0 +- U1/sqrt(3), then L0, L1x, L1y.
+template <typename real>
+__device__ __forceinline__ void cell_operator(const Row<real> &cur, real FE0, real FE1, real FE2,
+                                              real FW0, real FW1, real FW2, real GN0, real GN1,
+                                              real GN2, real GS0, real GS1, real GS2, real zbx,
+                                              real zby, real g, real tol, real idx, real idy,
+                                              real *Lop) {
+  const real half = real(0.5), is3 = real(kInvSqrt3), two_g = real(2) * g;
+  const real tg3 = real(2) * g / real(3);
+  const real e1 = cur.eh * cur.eu, e2 = cur.eh * cur.ev;
+  const real w1 = cur.wh * cur.wu, w2 = cur.wh * cur.wv;
+  const real A0 = half * (cur.eh + cur.wh), A1 = half * (e1 + w1), A2 = half * (e2 + w2);
+  const real B0 = half * (cur.eh - cur.wh), B1 = half * (e1 - w1), B2 = half * (e2 - w2);
+  const real n1 = cur.nh * cur.nu, n2 = cur.nh * cur.nv;
+  const real s1 = cur.sh * cur.su, s2 = cur.sh * cur.sv;
+  const real C0 = half * (cur.nh + cur.sh), C1 = half * (n1 + s1), C2 = half * (n2 + s2);
+  const real D0 = half * (cur.nh - cur.sh), D1 = half * (n1 - s1), D2 = half * (n2 - s2);
+  real Fp0, Fp1, Fp2, Fm0, Fm1, Fm2, Gp0, Gp1, Gp2, Gm0, Gm1, Gm2;
+  flux_x(A0 + B0 * is3, A1 + B1 * is3, A2 + B2 * is3, g, tol, Fp0, Fp1, Fp2);
+  flux_x(A0 - B0 * is3, A1 - B1 * is3, A2 - B2 * is3, g, tol, Fm0, Fm1, Fm2);
+  flux_y(C0 + D0 * is3, C1 + D1 * is3, C2 + D2 * is3, g, tol, Gp0, Gp1, Gp2);
+  flux_y(C0 - D0 * is3, C1 - D1 * is3, C2 - D2 * is3, g, tol, Gm0, Gm1, Gm2);
+  const real m3x = real(-3) * idx, m3y = real(-3) * idy;
+  Lop[0] = -(FE0 - FW0) * idx - (GN0 - GS0) * idy;
+  Lop[3] = -(FE1 - FW1) * idx - (GN1 - GS1) * idy - two_g * A0 * zbx * idx;
+  Lop[6] = -(FE2 - FW2) * idx - (GN2 - GS2) * idy - two_g * C0 * zby * idy;
+  Lop[1] = m3x * ((FE0 + FW0) - (Fp0 + Fm0));
+  Lop[4] = m3x * ((FE1 + FW1) - (Fp1 + Fm1) + tg3 * B0 * zbx);
+  Lop[7] = m3x * ((FE2 + FW2) - (Fp2 + Fm2));
+  Lop[2] = m3y * ((GN0 + GS0) - (Gp0 + Gm0));
+  Lop[5] = m3y * ((GN1 + GS1) - (Gp1 + Gm1));
+  Lop[8] = m3y * ((GN2 + GS2) - (Gp2 + Gm2) + tg3 * D0 * zby);
+}
+
+// North face of a row (the y-face to the row above) as [mass, x-mom, y-mom];
+// an inflow segment on the north wall replaces the flux.  dN = max(0, -h_N^-)
+// for the wall revision of the bed at that face.
+template <typename real>
+__device__ __forceinline__ void north_face(const Row<real> &cur, const Row<real> &nxt, bool inflow,
+                                           real q, real g, real tol, real &G0, real &G1, real &G2,
+                                           real &dN) {
+  y_face(cur, nxt, g, tol, G0, G1, G2);
+  dN = dmax(real(0), -cur.nr);
+  if (inflow) {
+    inflow_flux(q, cur.nh, g, G0, G2);
+    G0 = -G0;
+    G1 = real(0);
+  }
+}
+
+// East face of every lane's cell (with the '+' limit of the lane to the east)
+// and its west face (the east face of the lane to the west), with inflow
+// segments on the west and east walls, and the wall-revision depths.
+template <typename real>
+__device__ __forceinline__ void east_west_faces(const Row<real> &cur, bool inW, real qW, bool inE,
+                                                real qE, real g, real tol, real &FE0, real &FE1,
+                                                real &FE2, real &FW0, real &FW1, real &FW2,
+                                                real &dE, real &dW) {
+  const real ph = __shfl_down(cur.wh, 1, 64);
+  const real pu = __shfl_down(cur.wu, 1, 64);
+  const real pv = __shfl_down(cur.wv, 1, 64);
+  hll(cur.eh, cur.eu, cur.ev, ph, pu, pv, g, tol, FE0, FE1, FE2);
+  if (inW) {
+    inflow_flux(qW, ph, g, FE0, FE1);
+    FE2 = real(0);
+  }
+  if (inE) {
+    inflow_flux(qE, cur.eh, g, FE0, FE1);
+    FE0 = -FE0;
+    FE2 = real(0);
+  }
+  dE = dmax(real(0), -cur.er);
+  FW0 = __shfl_up(FE0, 1, 64);
+  FW1 = __shfl_up(FE1, 1, 64);
+  FW2 = __shfl_up(FE2, 1, 64);
+  dW = __shfl_up(dE, 1, 64);
+}
+
+// Stage-2 bookkeeping of a new cell state o: Courant candidate, NaN and
+// negative-depth flags, and gauge samples of the planar solution (Eq. 2).
+template <typename real>
+__device__ __forceinline__ void new_state_checks(const Scen<real> &s, const real *o, long long cidx,
+                                                 unsigned long long gmask, long long gslot, real g,
+                                                 real tol, double &mloc, unsigned &flags) {
+  const double m = cfl_candidate(o[0], o[3], o[6], g, tol, s.dx, s.dy);
+  mloc = m < mloc ? m : mloc;
+  if (o[0] != o[0]) flags |= kFlagNaN;
+  if (o[0] < real(0)) flags |= kFlagNegative;
+  if (gmask) {
+    for (int k = 0; k < s.ng; ++k) {
+      if (!((gmask >> k) & 1ull)) continue;
+      if (s.g_cell[k] != (int)cidx) continue;
+      const real xi = s.g_xi[k], ze = s.g_zeta[k];
+      const real h = o[0] + xi * o[1] + ze * o[2];
+      const real qx = o[3] + xi * o[4] + ze * o[5];
+      const real qy = o[6] + xi * o[7] + ze * o[8];
+      real *gb = s.g_buf + (gslot + k) * 4;
+      gb[0] = h;
+      gb[1] = h + s.g_z[k];
+      gb[2] = h > tol ? qx / h : real(0);
+      gb[3] = h > tol ? qy / h : real(0);
+    }
+  }
+}
+
+// Gauges inside this wavefront's output rectangle, as a bit mask.
+template <typename real>
+__device__ __forceinline__ unsigned long long gauge_mask(const Scen<real> &s, int c0, int cols,
+                                                         int j0, int j1) {
+  unsigned long long gmask = 0;
+  for (int k = 0; k < s.ng; ++k) {
+    const int gc = s.g_cell[k];
+    const int gj = gc / s.nx, gi = gc - gj * s.nx;
+    if (gj >= j0 && gj < j1 && gi >= c0 && gi < c0 + cols) gmask |= 1ull << k;
+  }
+  return gmask;
+}
+
+// Wave minimum of the Courant candidates and one atomic per wavefront on the
+// order-preserving bit pattern of a positive double; flags are OR-ed in.
+template <typename real>
+__device__ __forceinline__ void publish_min(const Scen<real> &s, int lane, double mloc,
+                                            unsigned flags) {
+  const unsigned long long bits = wave_min_u64((unsigned long long)__double_as_longlong(mloc));
+  const unsigned long long anyflag = __ballot(flags != 0);
+  if (lane == 0 && bits != kInfBits) {
+    const unsigned long long seen =
+        __hip_atomic_load(&s.ctrl->minbits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (bits < seen) atomicMin(&s.ctrl->minbits, bits);
+  }
+  if (anyflag && flags) atomicOr(&s.ctrl->flags, flags);
+}
+
 // Raw planes of one row for the lane's column (clamped into the grid) and,
 // in stage 1, its Manning value.
 template <typename real, int STAGE>
@@ -124,8 +260,7 @@ __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch
   if (!(dtd > 0.0)) return;
 
   const real dt = (real)dtd, g = (real)c.g, tol = (real)c.tol;
-  const real half = real(0.5), is3 = real(kInvSqrt3), two_g = real(2) * g;
-  const real tg3 = real(2) * g / real(3);
+  const real half = real(0.5);
   const int strip = item % L.nstrips, seg = item / L.nstrips;
   const int i = strip * kStripNL + lane - 1;
   const int j0 = seg * L.R, j1 = min(j0 + L.R, s.ny);
@@ -149,12 +284,7 @@ __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch
   unsigned long long gmask = 0;
   long long gslot = 0;
   if (STAGE == 2 && s.ng > 0) {
-    const int c0 = strip * kStripNL;
-    for (int k = 0; k < s.ng; ++k) {
-      const int gc = s.g_cell[k];
-      const int gj = gc / s.nx, gi = gc - gj * s.nx;
-      if (gj >= j0 && gj < j1 && gi >= c0 && gi < c0 + kStripNL) gmask |= 1ull << k;
-    }
+    gmask = gauge_mask(s, strip * kStripNL, kStripNL, j0, j1);
     gslot = (s.ctrl->gauge_written % s.g_cap) * s.ng;
   }
 
@@ -188,36 +318,12 @@ __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch
 
     build_row<real, STAGE>(rawA, j + 1, s.ny, mx, rain, gdt, tol, nxt);
 
-    // north face of row j
-    real GN0, GN1, GN2;
-    y_face(cur, nxt, g, tol, GN0, GN1, GN2);
-    const real dN = dmax(real(0), -cur.nr);
-    if (j == s.ny - 1 && colN) {
-      inflow_flux(qN, cur.nh, g, GN0, GN2);
-      GN0 = -GN0;
-      GN1 = real(0);
-    }
-
-    // east face of this lane's cell; the west face comes from the lane to the west
-    const real ph = __shfl_down(cur.wh, 1, 64);
-    const real pu = __shfl_down(cur.wu, 1, 64);
-    const real pv = __shfl_down(cur.wv, 1, 64);
-    real FE0, FE1, FE2;
-    hll(cur.eh, cur.eu, cur.ev, ph, pu, pv, g, tol, FE0, FE1, FE2);
-    if (faceW && j >= s.seg_first[0] && j <= s.seg_last[0]) {
-      inflow_flux(qW, ph, g, FE0, FE1);
-      FE2 = real(0);
-    }
-    if (faceE && j >= s.seg_first[1] && j <= s.seg_last[1]) {
-      inflow_flux(qE, cur.eh, g, FE0, FE1);
-      FE0 = -FE0;
-      FE2 = real(0);
-    }
-    const real dE = dmax(real(0), -cur.er);
-    const real FW0 = __shfl_up(FE0, 1, 64);
-    const real FW1 = __shfl_up(FE1, 1, 64);
-    const real FW2 = __shfl_up(FE2, 1, 64);
-    const real dW = __shfl_up(dE, 1, 64);
+    real GN0, GN1, GN2, dN;
+    north_face(cur, nxt, j == s.ny - 1 && colN, qN, g, tol, GN0, GN1, GN2, dN);
+    real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
+    east_west_faces(cur, faceW && j >= s.seg_first[0] && j <= s.seg_last[0], qW,
+                    faceE && j >= s.seg_first[1] && j <= s.seg_last[1], qE, g, tol, FE0, FE1, FE2,
+                    FW0, FW1, FW2, dE, dW);
 
     if (own) {
       const long long cidx = (long long)j * s.nx + i;
@@ -228,38 +334,10 @@ __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch
         W1[0] += rain;
         apply_friction(W1, gdt * ownC.n * ownC.n, tol);
       }
-      // dummy modes, Eq. (5)
-      const real e1 = cur.eh * cur.eu, e2 = cur.eh * cur.ev;
-      const real w1 = cur.wh * cur.wu, w2 = cur.wh * cur.wv;
-      const real A0 = half * (cur.eh + cur.wh), A1 = half * (e1 + w1), A2 = half * (e2 + w2);
-      const real B0 = half * (cur.eh - cur.wh), B1 = half * (e1 - w1), B2 = half * (e2 - w2);
-      const real n1 = cur.nh * cur.nu, n2 = cur.nh * cur.nv;
-      const real s1 = cur.sh * cur.su, s2 = cur.sh * cur.sv;
-      const real C0 = half * (cur.nh + cur.sh), C1 = half * (n1 + s1), C2 = half * (n2 + s2);
-      const real D0 = half * (cur.nh - cur.sh), D1 = half * (n1 - s1), D2 = half * (n2 - s2);
-      // revised bed slopes: z*_face = z_face - max(0, -h^-) on each face
-      const real zbx = ownC.z1x - half * dE + half * dW;
-      const real zby = ownC.z1y - half * dN + half * dS;
-      // physical fluxes at the Gauss points
-      real Fp0, Fp1, Fp2, Fm0, Fm1, Fm2, Gp0, Gp1, Gp2, Gm0, Gm1, Gm2;
-      flux_x(A0 + B0 * is3, A1 + B1 * is3, A2 + B2 * is3, g, tol, Fp0, Fp1, Fp2);
-      flux_x(A0 - B0 * is3, A1 - B1 * is3, A2 - B2 * is3, g, tol, Fm0, Fm1, Fm2);
-      flux_y(C0 + D0 * is3, C1 + D1 * is3, C2 + D2 * is3, g, tol, Gp0, Gp1, Gp2);
-      flux_y(C0 - D0 * is3, C1 - D1 * is3, C2 - D2 * is3, g, tol, Gm0, Gm1, Gm2);
-      // operators, Eq. (4)
       real Lop[9];
-      const real idx = s.idx, idy = s.idy;
-      const real m3x = real(-3) * idx, m3y = real(-3) * idy;
-      Lop[0] = -(FE0 - FW0) * idx - (GN0 - GS0) * idy;
-      Lop[3] = -(FE1 - FW1) * idx - (GN1 - GS1) * idy - two_g * A0 * zbx * idx;
-      Lop[6] = -(FE2 - FW2) * idx - (GN2 - GS2) * idy - two_g * C0 * zby * idy;
-      Lop[1] = m3x * ((FE0 + FW0) - (Fp0 + Fm0));
-      Lop[4] = m3x * ((FE1 + FW1) - (Fp1 + Fm1) + tg3 * B0 * zbx);
-      Lop[7] = m3x * ((FE2 + FW2) - (Fp2 + Fm2));
-      Lop[2] = m3y * ((GN0 + GS0) - (Gp0 + Gm0));
-      Lop[5] = m3y * ((GN1 + GS1) - (Gp1 + Gm1));
-      Lop[8] = m3y * ((GN2 + GS2) - (Gp2 + Gm2) + tg3 * D0 * zby);
-
+      cell_operator(cur, FE0, FE1, FE2, FW0, FW1, FW2, GN0, GN1, GN2, GS0, GS1, GS2,
+                    ownC.z1x - half * dE + half * dW, ownC.z1y - half * dN + half * dS, g, tol,
+                    s.idx, s.idy, Lop);
       real o[9];
       if (STAGE == 1) {
 #pragma unroll
@@ -273,27 +351,7 @@ __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch
 #pragma unroll
       for (int k = 0; k < 9; ++k) st_at(dst + k * s.P, off, o[k]);
 
-      if (STAGE == 2) {
-        const double m = cfl_candidate(o[0], o[3], o[6], g, tol, s.dx, s.dy);
-        mloc = m < mloc ? m : mloc;
-        if (o[0] != o[0]) flags |= kFlagNaN;
-        if (o[0] < real(0)) flags |= kFlagNegative;
-        if (gmask) {
-          for (int k = 0; k < s.ng; ++k) {
-            if (!((gmask >> k) & 1ull)) continue;
-            if (s.g_cell[k] != (int)cidx) continue;
-            const real xi = s.g_xi[k], ze = s.g_zeta[k];
-            const real h = o[0] + xi * o[1] + ze * o[2];
-            const real qx = o[3] + xi * o[4] + ze * o[5];
-            const real qy = o[6] + xi * o[7] + ze * o[8];
-            real *gb = s.g_buf + (gslot + k) * 4;
-            gb[0] = h;
-            gb[1] = h + s.g_z[k];
-            gb[2] = h > tol ? qx / h : real(0);
-            gb[3] = h > tol ? qy / h : real(0);
-          }
-        }
-      }
+      if (STAGE == 2) new_state_checks(s, o, cidx, gmask, gslot, g, tol, mloc, flags);
     }
 
     cur = nxt;
@@ -304,16 +362,249 @@ __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch
     dS = dN;
   }
 
-  if (STAGE == 2) {
-    const unsigned long long bits = wave_min_u64((unsigned long long)__double_as_longlong(mloc));
-    const unsigned long long anyflag = __ballot(flags != 0);
-    if (lane == 0 && bits != kInfBits) {
-      const unsigned long long seen =
-          __hip_atomic_load(&s.ctrl->minbits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (bits < seen) atomicMin(&s.ctrl->minbits, bits);
-    }
-    if (anyflag && flags) atomicOr(&s.ctrl->flags, flags);
+  if (STAGE == 2) publish_min(s, lane, mloc, flags);
+}
+
+// ---------------------------------------------------------------------------
+// DG2-LL: local slope limiting (Sec. 2.1.3, Eq. 6-7) before each stage.
+//
+// Halo of two cells: a wavefront owns 60 output columns (lanes 2..61) and a
+// lane keeps three consecutive rows of the unlimited stage input.  Row r is
+// limited in x with its neighbours from the lanes on either side (cross-lane
+// shuffles) and in y with rows r-1 and r+1 from its own registers.  Ghost
+// cells at distance d mirror the cell at distance d-1 inside the wall, so the
+// limiter evaluated on a ghost lane or row gives exactly the mirror image of
+// the limited interior cell, as a ghost of the limited state must be.
+// Stage 1 also stores the limited stage-1 input W1 for the RK average of
+// stage 2, which therefore reads neither U^n nor the Manning plane.
+// ---------------------------------------------------------------------------
+
+// Reflect an index up to two cells outside [0, n) back inside; m tells
+// whether an odd number of reflections was used.  Lanes beyond the grid (dead
+// lanes of the last strip) are clamped; their values are never used.
+__device__ __forceinline__ int reflect2(int i, int n, bool &m) {
+  m = false;
+  if (i < 0) {
+    i = -i - 1;
+    m = true;
   }
+  if (i >= n) {
+    i = 2 * n - i - 1;
+    m = !m;
+  }
+  if (i < 0) {
+    i = -i - 1;
+    m = !m;
+  }
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Unlimited stage input of one row and its bed modes.
+template <typename real>
+struct RowLL {
+  real W[9];
+  real z0, z1x, z1y;
+};
+
+template <typename real, int STAGE>
+__device__ __forceinline__ void load_row_ll(const Scen<real> &s, const real *src, int r, int ci,
+                                            bool mx, real rain, real gdt, real tol,
+                                            RowLL<real> &row) {
+  bool my;
+  const int rs = reflect2(r, s.ny, my);
+  const unsigned off = (unsigned)(rs * s.nx + ci) * (unsigned)sizeof(real);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) row.W[k] = ld_at(src + k * s.P, off);
+  row.z0 = ld_at(s.z, off);
+  row.z1x = ld_at(s.z + s.P, off);
+  row.z1y = ld_at(s.z + 2 * s.P, off);
+  real n = s.n_uniform;
+  if (STAGE == 1 && s.n) n = ld_at(s.n, off);
+  mirror(row.W, mx, my);
+  if (mx) row.z1x = -row.z1x;
+  if (my) row.z1y = -row.z1y;
+  if (STAGE == 1) {
+    row.W[0] += rain;
+    apply_friction(row.W, gdt * n * n, tol);
+  }
+}
+
+template <typename real>
+__device__ __forceinline__ real minmod3(real a, real b, real c) {
+  if (a > real(0) && b > real(0) && c > real(0)) return dmin(dmin(a, b), c);
+  if (a < real(0) && b < real(0) && c < real(0)) return dmax(dmax(a, b), c);
+  return real(0);
+}
+
+// One slope of Eq. (6)-(7) for a component with mean c0 and slope c1 in the
+// element, neighbours (p0, p1) ahead and (m0, m1) behind: the detector
+// max(|jump_p|, |jump_m|) > theta (d/2) max|c0 -+ c1/sqrt3| written without
+// division, then the generalised minmod.  Returns true and the limited slope
+// in out when limiting applies.
+template <typename real>
+__device__ __forceinline__ bool ll_slope(real c0, real c1, real p0, real p1, real m0, real m1,
+                                         real thr, real &out) {
+  const real jp = fabs((p0 - p1) - (c0 + c1));
+  const real jm = fabs((c0 - c1) - (m0 + m1));
+  const real is3 = real(kInvSqrt3);
+  const real sc = dmax(fabs(c0 - c1 * is3), fabs(c0 + c1 * is3));
+  if (!(dmax(jp, jm) > thr * sc)) return false;
+  out = minmod3(c1, p0 - c0, c0 - m0);
+  return true;
+}
+
+// Limited copy of the middle row c (rows m below, p above); x neighbours come
+// from the adjacent lanes.  thx = theta dx/2, thy = theta dy/2.
+template <typename real>
+__device__ __forceinline__ void limit_row(const RowLL<real> &m, const RowLL<real> &c,
+                                          const RowLL<real> &p, real thx, real thy, real tol,
+                                          real *out) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) out[k] = c.W[k];
+  const real e0 = c.W[0] + c.z0, ex = c.W[1] + c.z1x, ey = c.W[2] + c.z1y;  // eta modes
+  // x direction: neighbours from the lanes on either side
+  const real h0E = __shfl_down(c.W[0], 1, 64), h0W = __shfl_up(c.W[0], 1, 64);
+  const real e0E = __shfl_down(e0, 1, 64), e0W = __shfl_up(e0, 1, 64);
+  const real exE = __shfl_down(ex, 1, 64), exW = __shfl_up(ex, 1, 64);
+  const real u0E = __shfl_down(c.W[3], 1, 64), u0W = __shfl_up(c.W[3], 1, 64);
+  const real uxE = __shfl_down(c.W[4], 1, 64), uxW = __shfl_up(c.W[4], 1, 64);
+  const real v0E = __shfl_down(c.W[6], 1, 64), v0W = __shfl_up(c.W[6], 1, 64);
+  const real vxE = __shfl_down(c.W[7], 1, 64), vxW = __shfl_up(c.W[7], 1, 64);
+  real lim;
+  if (c.W[0] > tol && h0E > tol && h0W > tol) {
+    if (ll_slope(e0, ex, e0E, exE, e0W, exW, thx, lim)) out[1] = lim - c.z1x;
+    if (ll_slope(c.W[3], c.W[4], u0E, uxE, u0W, uxW, thx, lim)) out[4] = lim;
+    if (ll_slope(c.W[6], c.W[7], v0E, vxE, v0W, vxW, thx, lim)) out[7] = lim;
+  }
+  // y direction: rows below and above
+  if (c.W[0] > tol && p.W[0] > tol && m.W[0] > tol) {
+    if (ll_slope(e0, ey, p.W[0] + p.z0, p.W[2] + p.z1y, m.W[0] + m.z0, m.W[2] + m.z1y, thy, lim))
+      out[2] = lim - c.z1y;
+    if (ll_slope(c.W[3], c.W[5], p.W[3], p.W[5], m.W[3], m.W[5], thy, lim)) out[5] = lim;
+    if (ll_slope(c.W[6], c.W[8], p.W[6], p.W[8], m.W[6], m.W[8], thy, lim)) out[8] = lim;
+  }
+}
+
+template <typename real>
+__device__ __forceinline__ void limited_row(const RowLL<real> &m, const RowLL<real> &c,
+                                            const RowLL<real> &p, real thx, real thy, real tol,
+                                            Row<real> &row) {
+  limit_row(m, c, p, thx, thy, tol, row.W);
+  row_limits(row, tol);
+}
+
+template <typename real, int STAGE>
+__global__ void __launch_bounds__(256) k_stage_ll(Scen<real> s, Consts c, Launch L) {
+  const int lane = threadIdx.x & 63;
+  const int item = blockIdx.x * L.wpb + (threadIdx.x >> 6);
+  if (item >= L.nitems) return;
+  const double dtd = s.ctrl->dt;
+  if (!(dtd > 0.0)) return;
+
+  const real dt = (real)dtd, g = (real)c.g, tol = (real)c.tol;
+  const real half = real(0.5);
+  const real thx = (real)(c.theta * 0.5 * (double)s.dx), thy = (real)(c.theta * 0.5 * (double)s.dy);
+  const int strip = item % L.nstrips, seg = item / L.nstrips;
+  const int i = strip * kStripLL + lane - 2;
+  const int j0 = seg * L.R, j1 = min(j0 + L.R, s.ny);
+  const bool own = lane >= 2 && lane < 2 + kStripLL && i < s.nx;
+  bool mx;
+  const int ci = reflect2(i, s.nx, mx);
+  const real rain = (real)s.ctrl->rain;
+  const real gdt = g * dt;
+  const real *src = STAGE == 1 ? s.U : s.U1;
+  real *dst = STAGE == 1 ? s.U1 : const_cast<real *>(s.U);
+
+  const int si = STAGE - 1;
+  const real qW = (real)s.ctrl->qin[0][si], qE = (real)s.ctrl->qin[1][si];
+  const real qS = (real)s.ctrl->qin[2][si], qN = (real)s.ctrl->qin[3][si];
+  const bool faceW = (i == -1) && qW != real(0);
+  const bool faceE = (i == s.nx - 1) && qE != real(0);
+  const bool colS = qS != real(0) && i >= s.seg_first[2] && i <= s.seg_last[2];
+  const bool colN = qN != real(0) && i >= s.seg_first[3] && i <= s.seg_last[3];
+
+  unsigned long long gmask = 0;
+  long long gslot = 0;
+  if (STAGE == 2 && s.ng > 0) {
+    gmask = gauge_mask(s, strip * kStripLL, kStripLL, j0, j1);
+    gslot = (s.ctrl->gauge_written % s.g_cap) * s.ng;
+  }
+
+  RowLL<real> ra, rb, rc;  // unlimited input of rows j-1, j, j+1 (shifted as the march goes)
+  Row<real> cur, nxt;      // limited rows j and j+1 with their dummy limits
+  real GS0, GS1, GS2, dS;
+  {
+    RowLL<real> rz;
+    Row<real> prev;
+    load_row_ll<real, STAGE>(s, src, j0 - 2, ci, mx, rain, gdt, tol, rz);
+    load_row_ll<real, STAGE>(s, src, j0 - 1, ci, mx, rain, gdt, tol, ra);
+    load_row_ll<real, STAGE>(s, src, j0, ci, mx, rain, gdt, tol, rb);
+    load_row_ll<real, STAGE>(s, src, j0 + 1, ci, mx, rain, gdt, tol, rc);
+    limited_row(rz, ra, rb, thx, thy, tol, prev);
+    limited_row(ra, rb, rc, thx, thy, tol, cur);
+    y_face(prev, cur, g, tol, GS0, GS1, GS2);
+    dS = dmax(real(0), -prev.nr);
+    if (j0 == 0 && colS) {
+      inflow_flux(qS, cur.sh, g, GS0, GS2);
+      GS1 = real(0);
+    }
+  }
+
+  double mloc = __longlong_as_double((long long)kInfBits);
+  unsigned flags = 0;
+
+  for (int j = j0; j < j1; ++j) {
+    // ra, rb, rc hold rows j-1, j, j+1 (unlimited); bring in row j+2
+    RowLL<real> rd;
+    load_row_ll<real, STAGE>(s, src, j + 2, ci, mx, rain, gdt, tol, rd);
+    real W1[9];
+    const long long cidx = (long long)j * s.nx + i;
+    const unsigned off = (unsigned)cidx * (unsigned)sizeof(real);
+    if (STAGE == 2 && own) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) W1[k] = ld_at(s.W1 + k * s.P, off);
+    }
+    limited_row(rb, rc, rd, thx, thy, tol, nxt);
+
+    real GN0, GN1, GN2, dN;
+    north_face(cur, nxt, j == s.ny - 1 && colN, qN, g, tol, GN0, GN1, GN2, dN);
+    real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
+    east_west_faces(cur, faceW && j >= s.seg_first[0] && j <= s.seg_last[0], qW,
+                    faceE && j >= s.seg_first[1] && j <= s.seg_last[1], qE, g, tol, FE0, FE1, FE2,
+                    FW0, FW1, FW2, dE, dW);
+
+    if (own) {
+      real Lop[9];
+      cell_operator(cur, FE0, FE1, FE2, FW0, FW1, FW2, GN0, GN1, GN2, GS0, GS1, GS2,
+                    rb.z1x - half * dE + half * dW, rb.z1y - half * dN + half * dS, g, tol, s.idx,
+                    s.idy, Lop);
+      real o[9];
+      if (STAGE == 1) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) o[k] = cur.W[k] + dt * Lop[k];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) st_at(s.W1 + k * s.P, off, cur.W[k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) o[k] = half * (W1[k] + cur.W[k] + dt * Lop[k]);
+      }
+      wet_dry_fix(o, tol);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) st_at(dst + k * s.P, off, o[k]);
+      if (STAGE == 2) new_state_checks(s, o, cidx, gmask, gslot, g, tol, mloc, flags);
+    }
+
+    ra = rb;
+    rb = rc;
+    rc = rd;
+    cur = nxt;
+    GS0 = GN0;
+    GS1 = GN1;
+    GS2 = GN2;
+    dS = dN;
+  }
+
+  if (STAGE == 2) publish_min(s, lane, mloc, flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -498,13 +789,19 @@ Launch make_launch(int nx, int ny, int variant, int R, int wpb) {
 template <typename real>
 hipError_t launch_stage(int stage, int variant, const Scen<real> &s, const Consts &c,
                         const Launch &L, hipStream_t st) {
-  if (variant != 0) return hipErrorNotSupported;
   const dim3 block(64 * L.wpb);
   const dim3 grid((L.nitems + L.wpb - 1) / L.wpb);
-  if (stage == 1)
-    hipLaunchKernelGGL((k_stage_nl<real, 1>), grid, block, 0, st, s, c, L);
-  else
-    hipLaunchKernelGGL((k_stage_nl<real, 2>), grid, block, 0, st, s, c, L);
+  if (variant == 1) {
+    if (stage == 1)
+      hipLaunchKernelGGL((k_stage_ll<real, 1>), grid, block, 0, st, s, c, L);
+    else
+      hipLaunchKernelGGL((k_stage_ll<real, 2>), grid, block, 0, st, s, c, L);
+  } else {
+    if (stage == 1)
+      hipLaunchKernelGGL((k_stage_nl<real, 1>), grid, block, 0, st, s, c, L);
+    else
+      hipLaunchKernelGGL((k_stage_nl<real, 2>), grid, block, 0, st, s, c, L);
+  }
   return hipGetLastError();
 }
 

@@ -212,3 +212,76 @@ def test_from_dry_channel_filling_matches_oracle():
     _say("steps gpu %d oracle %d, max |dh0| %.3e" % (step, r.steps, np.abs(gpu[0] - r.U[0, 0].numpy()).max()))
     assert t == 20.0 and step == r.steps
     _assert_close(gpu, O.to_planes(r.U), 1e-10, "channel filling")
+
+
+@pytest.mark.parametrize("nx,ny,theta", [(70, 45, 1.0), (131, 9, 0.0), (2, 6, 0.5), (61, 61, 10.0)])
+def test_ll_one_step_random_state(nx, ny, theta):
+    """DG2-LL: shock detector (Eq. 6) and minmod (Eq. 7) on random wet/dry modes."""
+    _say("DG2-LL one step", nx, ny, "theta", theta)
+    modes, Z = WL.random_modes(nx, ny, seed=7 * nx + ny, slope=1.2)
+    rng = np.random.default_rng(nx * ny)
+    man = rng.uniform(0.0, 0.06, size=(ny, nx))
+    dx, dy, dt = 0.5, 1.0, 1e-3
+    s = _sim(nx, ny, dx, dy, Z, man, variant="LL", ll_threshold=theta)
+    s.set_state(modes, 0.0)
+    s.set_fixed_dt(dt)
+    s.step(1)
+    gpu = s.get_state()[0]
+    prm = O.Params(nx=nx, ny=ny, dx=dx, dy=dy, manning=O._t(man), fixed_dt=dt, variant="LL",
+                   theta=theta)
+    ref = O.step(O.from_planes(modes), 0.0, O.bed_from_corners(Z), prm, dt)
+    _assert_close(gpu, O.to_planes(ref), 1e-12, "LL one step")
+
+
+@pytest.mark.parametrize("theta", [10.0, 1.0])
+def test_ll_dam_break_matches_oracle(theta):
+    sc = WL.dambreak_bump(variant="LL", steps=300)
+    sc.theta = theta
+    _say("DG2-LL dam break 128x128 FP64, 300 steps, theta", theta)
+    s = dg2.sim_from_scenario(sc)
+    s.step(sc.steps)
+    gpu, t, step, _ = s.get_state()
+    U, bed, prm = O.setup(sc)
+    r = O.run(U, bed, prm, steps=sc.steps)
+    ref = O.to_planes(r.U)
+    dh = np.abs(gpu[:3] - ref[:3]).max()
+    _say("  max |dh| %.3e" % dh)
+    assert dh <= 1e-10
+    _assert_close(gpu, ref, 1e-10, "LL dam break")
+
+
+@pytest.mark.parametrize("theta,T", [(10.0, 15.0), (1.0, 6.0)])
+def test_ll_from_dry_inflow_matches_oracle(theta, T):
+    """Wetting front under DG2-LL.  With a low threshold the limiter's branch
+    decisions at the front amplify round-off: the oracle itself, perturbed by
+    one ulp of the inflow, drifts by 3e-11 after 6 s and by 0.1 after 15 s at
+    theta = 1 (3e-15 at theta = 10), so theta = 1 is compared over 6 s."""
+    nx, ny, dx = 48, 40, 2.0
+    X, Y = WL.corner_xy(nx, ny, dx, dx)
+    Z = WL.fbm_surface((ny + 1, nx + 1), 0.7, 2.0, 21) - 1.0 * (np.abs(Y - 40.0) <= 6.0)
+    s = _sim(nx, ny, dx, dx, Z, 0.035, variant="LL", dt_max=0.1, ll_threshold=theta)
+    s.set_boundary(dg2.WEST, dg2.BC_INFLOW_Q, 17, 22)
+    s.set_inflow_hydrograph(dg2.WEST, [0.0, 30.0], [0.0, 4.0])
+    s.set_initial_corners(np.zeros_like(Z), False)
+    s.run_to(T)
+    gpu, t, step, _ = s.get_state()
+    infl = [O.InflowBC(O.WEST, 17, 22, O._t([0.0, 30.0]), O._t([0.0, 4.0]))]
+    prm = O.Params(nx=nx, ny=ny, dx=dx, dy=dx, manning=0.035, dt_max=0.1, inflows=infl,
+                   variant="LL", theta=theta)
+    r = O.run(O.initial_state(Z, np.zeros_like(Z), False), O.bed_from_corners(Z), prm, t_end=T)
+    assert t == T and step == r.steps
+    _assert_close(gpu, O.to_planes(r.U), 1e-10, "LL channel filling")
+
+
+def test_ll_fp32_runs_and_conserves_mass():
+    sc = WL.dambreak_bump(variant="LL", precision="fp32", steps=200)
+    s = dg2.sim_from_scenario(sc)
+    m0 = s.diagnostics()[0]
+    s.step(sc.steps)
+    m1 = s.diagnostics()[0]
+    gpu = s.get_state()[0]
+    U, bed, prm = O.setup(sc)
+    ref = O.to_planes(O.run(U, bed, prm, steps=sc.steps).U)
+    _say("LL FP32: max |dh0| %.3e, mass drift %.2e" % (np.abs(gpu[0] - ref[0]).max(), (m1 - m0) / m0))
+    assert np.abs(gpu[0] - ref[0]).max() <= 2e-4
+    assert abs(m1 - m0) <= 1e-6 * m0
