@@ -32,9 +32,10 @@
  *     dg2_last_error(NULL) gives the last failure of dg2_create on this
  *     thread.  Invalid sizes or parameters, NaN inputs and negative depths,
  *     discharges or Manning values return DG2_EINVAL and change nothing.
- *   - Numerical failures found on the device (NaN, a mean depth below
- *     -1e-6 m) are latched and returned as DG2_ENUMERIC by the next
- *     dg2_sync, dg2_get_state, dg2_read_gauges or dg2_diagnostics.
+ *   - A NaN found in the state on the device is latched and returned as
+ *     DG2_ENUMERIC by the next dg2_sync, dg2_get_state, dg2_read_gauges or
+ *     dg2_diagnostics.  Depths are never clipped: a negative mean depth is
+ *     reported by dg2_diagnostics (min_h), not as an error.
  *   - Work is queued on the context's HIP stream; calls that return host
  *     data synchronise that stream.  A context must be used from one host
  *     thread at a time.
@@ -57,7 +58,7 @@ typedef enum {
   DG2_ENOMEM = -2,       /* device or host allocation failed             */
   DG2_EHIP = -3,         /* a HIP runtime call failed                    */
   DG2_ESTATE = -4,       /* call not valid in the current state          */
-  DG2_ENUMERIC = -5,     /* NaN or negative mean depth found on device   */
+  DG2_ENUMERIC = -5,     /* NaN found in the state on the device         */
   DG2_EUNSUPPORTED = -6  /* option not available in this build           */
 } dg2_status;
 
@@ -207,6 +208,62 @@ dg2_status dg2_state_layout(const dg2_ctx *ctx, size_t *bytes, size_t *plane_str
  * copied in; the buffer is borrowed and must outlive the context or the
  * next dg2_bind_device_state(ctx, NULL, 0), which returns to own memory. */
 dg2_status dg2_bind_device_state(dg2_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* ------------------------------------------------------------------------
+ * Batched ensemble.  A batch advances many independent scenarios (contexts of
+ * any grid size) together: each RK stage is one persistent launch whose
+ * wavefronts stride through the (scenario, strip, row-segment) work items of
+ * all members, and each scenario keeps its own device-resident time step,
+ * time, inflows, rain and Courant minimum, exactly as if it were stepped
+ * alone (results are bitwise those of dg2_step on each member).  Steps are
+ * replayed from a captured HIP graph.
+ * ------------------------------------------------------------------------ */
+typedef struct dg2_batch dg2_batch;
+
+/* Build a batch from n >= 1 fully set-up contexts of the same precision,
+ * variant, g, tol_dry and ll_threshold.  The contexts stay owned by the
+ * caller and must outlive the batch; their parameters are read now (call
+ * dg2_batch_refresh after changing them).  While the batch is in use, step
+ * members only through it; call dg2_batch_sync before reading a member with
+ * dg2_get_state, dg2_read_gauges or dg2_diagnostics.  hip_stream: borrowed
+ * stream, or NULL for one owned by the batch.  Errors: DG2_EINVAL (bad or
+ * mixed members), DG2_ENOMEM, DG2_EHIP. */
+dg2_status dg2_batch_create(dg2_ctx *const *members, int32_t n, void *hip_stream, dg2_batch **out);
+
+/* Release the batch's resources (not the members).  NULL-safe. */
+void dg2_batch_destroy(dg2_batch *b);
+
+/* Message of the last failing call on b (NULL: last dg2_batch_create failure). */
+const char *dg2_batch_last_error(const dg2_batch *b);
+
+/* Re-read the members' parameters (boundaries, hydrographs, rain, Manning,
+ * fixed dt, gauges, bound state buffers). */
+dg2_status dg2_batch_refresh(dg2_batch *b);
+
+/* Rows per wavefront (<= 0: built-in choice), wavefronts per workgroup (1, 2
+ * or 4) and steps per captured graph (<= 1: no graph, eager launches).
+ * Results do not depend on these. */
+dg2_status dg2_batch_set_launch(dg2_batch *b, int32_t rows_per_wave, int32_t waves_per_block,
+                                int32_t graph_steps);
+
+/* Time candidate rows-per-wavefront on the members' current states (restored
+ * afterwards), keep the fastest; budget_ms bounds the time spent.  The choice
+ * is returned in *rows (may be NULL). */
+dg2_status dg2_batch_autotune(dg2_batch *b, double budget_ms, int32_t *rows);
+
+/* Queue nsteps time steps of every member (asynchronous). */
+dg2_status dg2_batch_step(dg2_batch *b, int32_t nsteps);
+
+/* Advance every member to time T (each lands on T exactly); returns when all
+ * have arrived.  Later dg2_batch_step calls are no longer bounded by T. */
+dg2_status dg2_batch_run_to(dg2_batch *b, double T);
+
+/* Wait for the batch's queued work; DG2_ENUMERIC if a member latched a NaN. */
+dg2_status dg2_batch_sync(dg2_batch *b);
+
+/* Run nsteps steps bracketed by HIP events on the batch stream and return
+ * the average milliseconds per step (all members). */
+dg2_status dg2_batch_time_steps(dg2_batch *b, int32_t nsteps, double *ms_per_step);
 
 #ifdef __cplusplus
 }

@@ -809,3 +809,399 @@ dg2_status dg2_bind_device_state(dg2_ctx *c, void *ptr, size_t bytes) {
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Batched ensemble
+// ===========================================================================
+
+struct BatchItem {
+  int sid, strip, seg, pad;
+};
+
+struct dg2_batch {
+  std::vector<dg2_ctx *> m;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int f32 = 0, variant = 0;
+  Consts consts{};
+  void *d_scens = nullptr;
+  BatchItem *d_items = nullptr;
+  int nitems = 0, items_cap = 0;
+  Ctrl **d_ctrls = nullptr;
+  PlanArgs *d_plan = nullptr;
+  unsigned *d_status = nullptr, *h_status = nullptr;
+  int R = 0, R_user = 0, wpb = 4, graph_steps = 16;
+  int blocks1 = 0, blocks2 = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_batch_error;
+
+dg2_status bfail(dg2_batch *b, dg2_status s, const std::string &msg) {
+  if (b)
+    b->err = msg;
+  else
+    g_batch_error = msg;
+  return s;
+}
+
+dg2_status bhip(dg2_batch *b, hipError_t e, const char *what) {
+  return bfail(b, e == hipErrorOutOfMemory ? DG2_ENOMEM : DG2_EHIP,
+               std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define BCHK(b, expr, what)                               \
+  do {                                                    \
+    hipError_t _e = (expr);                               \
+    if (_e != hipSuccess) return bhip(b, _e, what);       \
+  } while (0)
+
+void drop_graph(dg2_batch *b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+}
+
+// Rows per wavefront: ~16k items over the whole batch, 4..32.
+int batch_rows(const dg2_batch *b) {
+  if (b->R_user > 0) return b->R_user;
+  const int cols = b->variant == 1 ? kStripLL : kStripNL;
+  long long lanes_rows = 0;
+  for (auto *c : b->m) lanes_rows += (long long)((c->cfg.nx + cols - 1) / cols) * c->cfg.ny;
+  long long r = lanes_rows / 16384;
+  return (int)(r < 4 ? 4 : (r > 32 ? 32 : r));
+}
+
+dg2_status build_items(dg2_batch *b) {
+  b->R = batch_rows(b);
+  const int cols = b->variant == 1 ? kStripLL : kStripNL;
+  std::vector<BatchItem> items;
+  for (size_t k = 0; k < b->m.size(); ++k) {
+    const dg2_config &g = b->m[k]->cfg;
+    const int ns = (g.nx + cols - 1) / cols, ng = (g.ny + b->R - 1) / b->R;
+    for (int sg = 0; sg < ng; ++sg)
+      for (int st = 0; st < ns; ++st) items.push_back(BatchItem{(int)k, st, sg, 0});
+  }
+  if ((int)items.size() > b->items_cap) {
+    if (b->d_items) (void)hipFree(b->d_items);
+    b->d_items = nullptr;
+    BCHK(b, hipMalloc((void **)&b->d_items, items.size() * sizeof(BatchItem)), "batch items");
+    b->items_cap = (int)items.size();
+  }
+  BCHK(b, hipMemcpy(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice),
+       "batch items");
+  b->nitems = (int)items.size();
+  drop_graph(b);
+  return DG2_OK;
+}
+
+template <typename real>
+dg2_status upload_scens(dg2_batch *b) {
+  std::vector<Scen<real>> sc;
+  std::vector<PlanArgs> pa;
+  std::vector<Ctrl *> ctrls;
+  for (auto *c : b->m) {
+    sc.push_back(scen<real>(c));
+    pa.push_back(plan_args(c));
+    ctrls.push_back(c->ctrl);
+  }
+  const size_t n = b->m.size();
+  BCHK(b, hipMemcpy(b->d_scens, sc.data(), n * sizeof(Scen<real>), hipMemcpyHostToDevice), "scenarios");
+  BCHK(b, hipMemcpy(b->d_plan, pa.data(), n * sizeof(PlanArgs), hipMemcpyHostToDevice), "plans");
+  BCHK(b, hipMemcpy(b->d_ctrls, ctrls.data(), n * sizeof(Ctrl *), hipMemcpyHostToDevice), "ctrls");
+  return DG2_OK;
+}
+
+hipError_t batch_stage(dg2_batch *b, int stage) {
+  const int blocks = stage == 1 ? b->blocks1 : b->blocks2;
+  if (b->f32)
+    return launch_batch_stage<float>(stage, b->variant, (const Scen<float> *)b->d_scens, b->d_items,
+                                     b->nitems, b->consts, b->R, b->wpb, blocks, b->stream);
+  return launch_batch_stage<double>(stage, b->variant, (const Scen<double> *)b->d_scens, b->d_items,
+                                    b->nitems, b->consts, b->R, b->wpb, blocks, b->stream);
+}
+
+hipError_t batch_plan(dg2_batch *b, int mode, double t_end = 0.0, int set_tend = 0) {
+  return launch_plan_batch(b->d_ctrls, b->d_plan, (int)b->m.size(), mode, t_end, set_tend, b->stream);
+}
+
+dg2_status batch_queue_step(dg2_batch *b) {
+  BCHK(b, batch_stage(b, 1), "batch stage 1");
+  BCHK(b, batch_stage(b, 2), "batch stage 2");
+  BCHK(b, batch_plan(b, kPlanFinishStep), "batch plan");
+  return DG2_OK;
+}
+
+dg2_status ensure_graph(dg2_batch *b) {
+  if (b->gexec || b->graph_steps <= 1) return DG2_OK;
+  BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "graph capture");
+  dg2_status st = DG2_OK;
+  for (int k = 0; k < b->graph_steps && st == DG2_OK; ++k) st = batch_queue_step(b);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (st != DG2_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return bhip(b, e, "graph capture");
+  b->graph = g;
+  e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    drop_graph(b);
+    return bhip(b, e, "graph instantiate");
+  }
+  return DG2_OK;
+}
+
+// Queue n steps: whole graphs, then the remainder as eager launches.
+dg2_status batch_queue_steps(dg2_batch *b, int n) {
+  dg2_status st = ensure_graph(b);
+  if (st != DG2_OK) return st;
+  int done = 0;
+  if (b->gexec) {
+    for (; done + b->graph_steps <= n; done += b->graph_steps)
+      BCHK(b, hipGraphLaunch(b->gexec, b->stream), "graph launch");
+  }
+  for (; done < n; ++done)
+    if ((st = batch_queue_step(b)) != DG2_OK) return st;
+  return DG2_OK;
+}
+
+dg2_status batch_status(dg2_batch *b, unsigned *active, unsigned *flags) {
+  BCHK(b, launch_batch_status(b->d_ctrls, (int)b->m.size(), b->d_status, b->stream), "status");
+  BCHK(b, hipMemcpyAsync(b->h_status, b->d_status, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, b->stream),
+       "status");
+  BCHK(b, hipStreamSynchronize(b->stream), "status");
+  *active = b->h_status[0];
+  *flags = b->h_status[1];
+  return DG2_OK;
+}
+
+dg2_status batch_setup(dg2_batch *b) {
+  dg2_status st = b->f32 ? upload_scens<float>(b) : upload_scens<double>(b);
+  if (st != DG2_OK) return st;
+  if ((st = build_items(b)) != DG2_OK) return st;
+  b->blocks1 = b->f32 ? batch_blocks<float>(1, b->variant, b->wpb) : batch_blocks<double>(1, b->variant, b->wpb);
+  b->blocks2 = b->f32 ? batch_blocks<float>(2, b->variant, b->wpb) : batch_blocks<double>(2, b->variant, b->wpb);
+  const int need = (b->nitems + b->wpb - 1) / b->wpb;
+  if (b->blocks1 > need) b->blocks1 = need;
+  if (b->blocks2 > need) b->blocks2 = need;
+  if (b->blocks1 < 1) b->blocks1 = 1;
+  if (b->blocks2 < 1) b->blocks2 = 1;
+  return DG2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dg2_batch_last_error(const dg2_batch *b) { return b ? b->err.c_str() : g_batch_error.c_str(); }
+
+void dg2_batch_destroy(dg2_batch *b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  void *bufs[] = {b->d_scens, b->d_items, b->d_ctrls, b->d_plan, b->d_status};
+  for (void *p : bufs)
+    if (p) (void)hipFree(p);
+  if (b->h_status) (void)hipHostFree(b->h_status);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+dg2_status dg2_batch_create(dg2_ctx *const *members, int32_t n, void *hip_stream, dg2_batch **out) {
+  if (!out) return bfail(nullptr, DG2_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!members || n < 1) return bfail(nullptr, DG2_EINVAL, "need n >= 1 members");
+  const dg2_ctx *c0 = members[0];
+  for (int k = 0; k < n; ++k) {
+    const dg2_ctx *c = members[k];
+    if (!c) return bfail(nullptr, DG2_EINVAL, "NULL member");
+    if (c->cfg.prec != c0->cfg.prec || c->cfg.variant != c0->cfg.variant || c->cfg.g != c0->cfg.g ||
+        c->cfg.tol_dry != c0->cfg.tol_dry || c->cfg.ll_threshold != c0->cfg.ll_threshold)
+      return bfail(nullptr, DG2_EINVAL, "members differ in precision, variant, g, tol_dry or threshold");
+  }
+  dg2_batch *b = new (std::nothrow) dg2_batch();
+  if (!b) return bfail(nullptr, DG2_ENOMEM, "host allocation failed");
+  auto bail = [&](dg2_status s) {
+    g_batch_error = b->err;
+    dg2_batch_destroy(b);
+    return s;
+  };
+  b->m.assign(members, members + n);
+  b->f32 = c0->f32;
+  b->variant = c0->cfg.variant;
+  b->consts = consts(c0);
+  hipError_t e;
+  if (hip_stream) {
+    b->stream = (hipStream_t)hip_stream;
+  } else {
+    e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(bhip(b, e, "stream"));
+    b->own_stream = true;
+  }
+  for (auto *c : b->m) {
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return bail(bhip(b, e, "member sync"));
+  }
+  const size_t ssz = b->f32 ? sizeof(Scen<float>) : sizeof(Scen<double>);
+  if ((e = hipMalloc(&b->d_scens, n * ssz)) != hipSuccess) return bail(bhip(b, e, "scenarios"));
+  if ((e = hipMalloc((void **)&b->d_ctrls, n * sizeof(Ctrl *))) != hipSuccess) return bail(bhip(b, e, "ctrls"));
+  if ((e = hipMalloc((void **)&b->d_plan, n * sizeof(PlanArgs))) != hipSuccess) return bail(bhip(b, e, "plans"));
+  if ((e = hipMalloc((void **)&b->d_status, 2 * sizeof(unsigned))) != hipSuccess) return bail(bhip(b, e, "status"));
+  if ((e = hipHostMalloc((void **)&b->h_status, 2 * sizeof(unsigned), hipHostMallocDefault)) != hipSuccess)
+    return bail(bhip(b, e, "status"));
+  dg2_status st = batch_setup(b);
+  if (st != DG2_OK) return bail(st);
+  *out = b;
+  return DG2_OK;
+}
+
+dg2_status dg2_batch_refresh(dg2_batch *b) {
+  if (!b) return DG2_EINVAL;
+  BCHK(b, hipStreamSynchronize(b->stream), "sync");
+  for (auto *c : b->m) BCHK(b, hipStreamSynchronize(c->stream), "member sync");
+  return batch_setup(b);
+}
+
+dg2_status dg2_batch_set_launch(dg2_batch *b, int32_t rows, int32_t wpb, int32_t graph_steps) {
+  if (!b) return DG2_EINVAL;
+  if (wpb != 1 && wpb != 2 && wpb != 4) return bfail(b, DG2_EINVAL, "waves per block must be 1, 2 or 4");
+  BCHK(b, hipStreamSynchronize(b->stream), "sync");
+  b->R_user = rows > 0 ? rows : 0;
+  b->wpb = wpb;
+  b->graph_steps = graph_steps > 1 ? graph_steps : 1;
+  return batch_setup(b);
+}
+
+dg2_status dg2_batch_step(dg2_batch *b, int32_t nsteps) {
+  if (!b) return DG2_EINVAL;
+  if (nsteps < 0) return bfail(b, DG2_EINVAL, "nsteps must be >= 0");
+  BCHK(b, batch_plan(b, kPlanOnly, std::numeric_limits<double>::infinity(), 1), "plan");
+  return batch_queue_steps(b, nsteps);
+}
+
+dg2_status dg2_batch_sync(dg2_batch *b) {
+  if (!b) return DG2_EINVAL;
+  unsigned active = 0, flags = 0;
+  dg2_status st = batch_status(b, &active, &flags);
+  if (st != DG2_OK) return st;
+  if (flags & kFlagNaN) return bfail(b, DG2_ENUMERIC, "NaN in a member's state");
+  return DG2_OK;
+}
+
+dg2_status dg2_batch_run_to(dg2_batch *b, double T) {
+  if (!b) return DG2_EINVAL;
+  if (!std::isfinite(T)) return bfail(b, DG2_EINVAL, "T must be finite");
+  BCHK(b, batch_plan(b, kPlanOnly, T, 1), "plan");
+  const int chunk = b->graph_steps > 1 ? b->graph_steps : 32;
+  for (long long guard = 0;; guard += chunk) {
+    unsigned active = 0, flags = 0;
+    dg2_status st = batch_status(b, &active, &flags);
+    if (st != DG2_OK) return st;
+    if (flags & kFlagNaN) return bfail(b, DG2_ENUMERIC, "NaN in a member's state");
+    if (active == 0) break;
+    if (guard > (1ll << 31)) return bfail(b, DG2_ESTATE, "run_to exceeded 2^31 steps");
+    if ((st = batch_queue_steps(b, chunk)) != DG2_OK) return st;
+  }
+  // a member whose step collapsed to zero before T is a numerical failure
+  for (auto *c : b->m) {
+    Ctrl h;
+    BCHK(b, hipMemcpy(&h, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost), "ctrl");
+    if (h.t < T) return bfail(b, DG2_ENUMERIC, "a member's time step collapsed before T");
+  }
+  return DG2_OK;
+}
+
+dg2_status dg2_batch_time_steps(dg2_batch *b, int32_t nsteps, double *ms) {
+  if (!b) return DG2_EINVAL;
+  if (nsteps < 1) return bfail(b, DG2_EINVAL, "nsteps must be >= 1");
+  BCHK(b, batch_plan(b, kPlanOnly, std::numeric_limits<double>::infinity(), 1), "plan");
+  dg2_status st = ensure_graph(b);
+  if (st != DG2_OK) return st;
+  hipEvent_t e0, e1;
+  BCHK(b, hipEventCreate(&e0), "event");
+  BCHK(b, hipEventCreate(&e1), "event");
+  hipError_t e = hipEventRecord(e0, b->stream);
+  if (e == hipSuccess) st = batch_queue_steps(b, nsteps);
+  if (e == hipSuccess && st == DG2_OK) e = hipEventRecord(e1, b->stream);
+  if (e == hipSuccess && st == DG2_OK) e = hipEventSynchronize(e1);
+  float t = 0;
+  if (e == hipSuccess && st == DG2_OK) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != DG2_OK) return st;
+  if (e != hipSuccess) return bhip(b, e, "timing");
+  if (ms) *ms = t / nsteps;
+  return dg2_batch_sync(b);
+}
+
+dg2_status dg2_batch_autotune(dg2_batch *b, double budget_ms, int32_t *rows) {
+  if (!b) return DG2_EINVAL;
+  if (!(budget_ms > 0)) return bfail(b, DG2_EINVAL, "budget must be > 0");
+  BCHK(b, hipStreamSynchronize(b->stream), "sync");
+  // save every member's state and control block
+  size_t total = 0;
+  for (auto *c : b->m) total += 9 * (size_t)c->P * c->esz;
+  void *save = nullptr;
+  BCHK(b, hipMalloc(&save, total + b->m.size() * sizeof(Ctrl)), "autotune scratch");
+  auto copy_all = [&](bool to_save) -> hipError_t {
+    size_t off = 0;
+    for (auto *c : b->m) {
+      const size_t bytes = 9 * (size_t)c->P * c->esz;
+      char *sv = (char *)save + off;
+      hipError_t e = to_save ? hipMemcpyAsync(sv, c->U, bytes, hipMemcpyDeviceToDevice, b->stream)
+                             : hipMemcpyAsync(c->U, sv, bytes, hipMemcpyDeviceToDevice, b->stream);
+      if (e != hipSuccess) return e;
+      off += bytes;
+    }
+    for (size_t k = 0; k < b->m.size(); ++k) {
+      char *sv = (char *)save + total + k * sizeof(Ctrl);
+      hipError_t e = to_save ? hipMemcpyAsync(sv, b->m[k]->ctrl, sizeof(Ctrl), hipMemcpyDeviceToDevice, b->stream)
+                             : hipMemcpyAsync(b->m[k]->ctrl, sv, sizeof(Ctrl), hipMemcpyDeviceToDevice, b->stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipStreamSynchronize(b->stream);
+  };
+  hipError_t e = copy_all(true);
+  if (e != hipSuccess) {
+    (void)hipFree(save);
+    return bhip(b, e, "autotune save");
+  }
+  const int keep_user = b->R_user;
+  const int cand[] = {4, 8, 12, 16, 24, 32};
+  double best = 1e300, spent = 0;
+  int bestR = batch_rows(b);
+  dg2_status st = DG2_OK;
+  for (int R : cand) {
+    b->R_user = R;
+    if ((st = batch_setup(b)) != DG2_OK) break;
+    double ms = 0;
+    st = dg2_batch_time_steps(b, 4, &ms);
+    e = copy_all(false);
+    if (st != DG2_OK) break;
+    if (e != hipSuccess) {
+      st = bhip(b, e, "autotune restore");
+      break;
+    }
+    if (ms < best) {
+      best = ms;
+      bestR = R;
+    }
+    spent += 5 * ms;
+    if (spent > budget_ms) break;
+  }
+  (void)hipFree(save);
+  b->R_user = st == DG2_OK ? bestR : keep_user;
+  dg2_status st2 = batch_setup(b);
+  if (st != DG2_OK) return st;
+  if (rows) *rows = bestR;
+  return st2;
+}
+
+}  // extern "C"

@@ -60,6 +60,20 @@ template <typename real>
 hipError_t launch_diag(const Scen<real> &s, const Consts &c, double *partials, int nblocks,
                        double *out4, hipStream_t st);
 
+// Batched ensemble: items are (scenario, strip, segment, pad) int quadruples.
+template <typename real>
+hipError_t launch_batch_stage(int stage, int variant, const Scen<real> *scens, const void *items,
+                              int nitems, const Consts &c, int R, int wpb, int blocks,
+                              hipStream_t st);
+
+hipError_t launch_plan_batch(Ctrl *const *ctrls, const PlanArgs *pa, int n, int mode, double t_end,
+                             int set_tend, hipStream_t st);
+
+hipError_t launch_batch_status(Ctrl *const *ctrls, int n, unsigned *out, hipStream_t st);
+
+template <typename real>
+int batch_blocks(int stage, int variant, int wpb);
+
 enum PlanMode { kPlanOnly = 0, kPlanFromMin = 1, kPlanFinishStep = 2 };
 
 }  // namespace dg2

@@ -252,18 +252,15 @@ __device__ __forceinline__ void load_own(const Scen<real> &s, long long cidx, Ow
 // arithmetic of that row.  Prefetching the own data a row earlier as well
 // costs more registers than it gains.
 template <typename real, int STAGE>
-__global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch L) {
-  const int lane = threadIdx.x & 63;
-  const int item = blockIdx.x * L.wpb + (threadIdx.x >> 6);
-  if (item >= L.nitems) return;
+__device__ __forceinline__ void march_nl(const Scen<real> &s, const Consts &c, int strip, int seg,
+                                         int R, int lane) {
   const double dtd = s.ctrl->dt;
   if (!(dtd > 0.0)) return;
 
   const real dt = (real)dtd, g = (real)c.g, tol = (real)c.tol;
   const real half = real(0.5);
-  const int strip = item % L.nstrips, seg = item / L.nstrips;
   const int i = strip * kStripNL + lane - 1;
-  const int j0 = seg * L.R, j1 = min(j0 + L.R, s.ny);
+  const int j0 = seg * R, j1 = min(j0 + R, s.ny);
   const bool own = lane >= 1 && lane <= kStripNL && i < s.nx;
   const int ci = i < 0 ? 0 : (i >= s.nx ? s.nx - 1 : i);
   const bool mx = (i < 0) || (i >= s.nx);
@@ -363,6 +360,13 @@ __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch
   }
 
   if (STAGE == 2) publish_min(s, lane, mloc, flags);
+}
+
+template <typename real, int STAGE>
+__global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch L) {
+  const int item = blockIdx.x * L.wpb + (threadIdx.x >> 6);
+  if (item >= L.nitems) return;
+  march_nl<real, STAGE>(s, c, item % L.nstrips, item / L.nstrips, L.R, threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------------------
@@ -494,19 +498,16 @@ __device__ __forceinline__ void limited_row(const RowLL<real> &m, const RowLL<re
 }
 
 template <typename real, int STAGE>
-__global__ void __launch_bounds__(256) k_stage_ll(Scen<real> s, Consts c, Launch L) {
-  const int lane = threadIdx.x & 63;
-  const int item = blockIdx.x * L.wpb + (threadIdx.x >> 6);
-  if (item >= L.nitems) return;
+__device__ __forceinline__ void march_ll(const Scen<real> &s, const Consts &c, int strip, int seg,
+                                         int R, int lane) {
   const double dtd = s.ctrl->dt;
   if (!(dtd > 0.0)) return;
 
   const real dt = (real)dtd, g = (real)c.g, tol = (real)c.tol;
   const real half = real(0.5);
   const real thx = (real)(c.theta * 0.5 * (double)s.dx), thy = (real)(c.theta * 0.5 * (double)s.dy);
-  const int strip = item % L.nstrips, seg = item / L.nstrips;
   const int i = strip * kStripLL + lane - 2;
-  const int j0 = seg * L.R, j1 = min(j0 + L.R, s.ny);
+  const int j0 = seg * R, j1 = min(j0 + R, s.ny);
   const bool own = lane >= 2 && lane < 2 + kStripLL && i < s.nx;
   bool mx;
   const int ci = reflect2(i, s.nx, mx);
@@ -607,6 +608,46 @@ __global__ void __launch_bounds__(256) k_stage_ll(Scen<real> s, Consts c, Launch
   if (STAGE == 2) publish_min(s, lane, mloc, flags);
 }
 
+template <typename real, int STAGE>
+__global__ void __launch_bounds__(256) k_stage_ll(Scen<real> s, Consts c, Launch L) {
+  const int item = blockIdx.x * L.wpb + (threadIdx.x >> 6);
+  if (item >= L.nitems) return;
+  march_ll<real, STAGE>(s, c, item % L.nstrips, item / L.nstrips, L.R, threadIdx.x & 63);
+}
+
+// ---------------------------------------------------------------------------
+// Batched ensemble: one persistent launch per stage advances every scenario
+// of a batch.  The work list holds (scenario, strip, segment) items of all
+// scenarios; the resident wavefronts stride through it, each item running the
+// same march as the single-scenario kernels on that scenario's buffers with
+// that scenario's own dt, time, inflows and Courant minimum.  Items of
+// scenarios that are idle (dt = 0, e.g. already at their target time) return
+// at once.
+// ---------------------------------------------------------------------------
+
+struct Item {
+  int sid, strip, seg, pad;
+};
+
+template <typename real, int STAGE, int VARIANT>
+__global__ void __launch_bounds__(256) k_batch_stage(const Scen<real> *__restrict__ scens,
+                                                     const Item *__restrict__ items, int nitems,
+                                                     Consts c, int R, int wpb) {
+  const int lane = threadIdx.x & 63;
+  const int nw = gridDim.x * wpb;
+  for (int it = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6)); it < nitems;
+       it += nw) {
+    const int sid = __builtin_amdgcn_readfirstlane(items[it].sid);
+    const int strip = __builtin_amdgcn_readfirstlane(items[it].strip);
+    const int seg = __builtin_amdgcn_readfirstlane(items[it].seg);
+    const Scen<real> s = scens[sid];
+    if (VARIANT == 1)
+      march_ll<real, STAGE>(s, c, strip, seg, R, lane);
+    else
+      march_nl<real, STAGE>(s, c, strip, seg, R, lane);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Step planner: one thread.  Finishes a step (t += dt, counters, gauge time),
 // takes the Courant minimum of the new state, and plans the next step size,
@@ -641,8 +682,7 @@ __device__ void plan_next(Ctrl *c, const PlanArgs &p) {
   }
 }
 
-__global__ void k_plan(Ctrl *c, PlanArgs p, int mode, double t_end, int set_tend) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void plan_step(Ctrl *c, const PlanArgs &p, int mode, double t_end, int set_tend) {
   if (set_tend) c->t_end = t_end;
   if (mode == kPlanFinishStep) {
     const double dt = c->dt;
@@ -663,6 +703,19 @@ __global__ void k_plan(Ctrl *c, PlanArgs p, int mode, double t_end, int set_tend
     c->minbits = kInfBits;
   }
   plan_next(c, p);
+}
+
+__global__ void k_plan(Ctrl *c, PlanArgs p, int mode, double t_end, int set_tend) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  plan_step(c, p, mode, t_end, set_tend);
+}
+
+// One thread per scenario of a batch.
+__global__ void k_plan_batch(Ctrl *const *ctrls, const PlanArgs *pa, int n, int mode,
+                             double t_end, int set_tend) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  plan_step(ctrls[k], pa[k], mode, t_end, set_tend);
 }
 
 // Courant minimum of the current state (after the state was set from the host).
@@ -828,6 +881,84 @@ hipError_t launch_diag(const Scen<real> &s, const Consts &c, double *partials, i
   return hipGetLastError();
 }
 
+template <typename real>
+hipError_t launch_batch_stage(int stage, int variant, const Scen<real> *scens, const void *items,
+                              int nitems, const Consts &c, int R, int wpb, int blocks,
+                              hipStream_t st) {
+  const Item *it = (const Item *)items;
+  const dim3 block(64 * wpb), grid(blocks);
+  if (variant == 1) {
+    if (stage == 1)
+      hipLaunchKernelGGL((k_batch_stage<real, 1, 1>), grid, block, 0, st, scens, it, nitems, c, R, wpb);
+    else
+      hipLaunchKernelGGL((k_batch_stage<real, 2, 1>), grid, block, 0, st, scens, it, nitems, c, R, wpb);
+  } else {
+    if (stage == 1)
+      hipLaunchKernelGGL((k_batch_stage<real, 1, 0>), grid, block, 0, st, scens, it, nitems, c, R, wpb);
+    else
+      hipLaunchKernelGGL((k_batch_stage<real, 2, 0>), grid, block, 0, st, scens, it, nitems, c, R, wpb);
+  }
+  return hipGetLastError();
+}
+
+// Scenarios still running (dt > 0 and t below their target) and the OR of
+// their error flags, for the host's progress check: out[0] = count, out[1] = flags.
+__global__ void k_batch_status(Ctrl *const *ctrls, int n, unsigned *out) {
+  __shared__ unsigned cnt, fl;
+  if (threadIdx.x == 0) {
+    cnt = 0;
+    fl = 0;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const Ctrl *c = ctrls[k];
+    if (c->dt > 0.0 && c->t < c->t_end) atomicAdd(&cnt, 1u);
+    if (c->flags) atomicOr(&fl, c->flags);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = cnt;
+    out[1] = fl;
+  }
+}
+
+hipError_t launch_batch_status(Ctrl *const *ctrls, int n, unsigned *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_status, dim3(1), dim3(256), 0, st, ctrls, n, out);
+  return hipGetLastError();
+}
+
+// Workgroups of the persistent batched launch: the number that can be
+// resident at once for this kernel and workgroup size on the device.
+template <typename real>
+int batch_blocks(int stage, int variant, int wpb) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1024;
+  const int threads = 64 * wpb;
+  hipError_t e;
+  if (variant == 1)
+    e = stage == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_stage<real, 1, 1>, threads, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_stage<real, 2, 1>, threads, 0);
+  else
+    e = stage == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_stage<real, 1, 0>, threads, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_stage<real, 2, 0>, threads, 0);
+  if (e != hipSuccess || per < 1) per = 1;
+  return per * cus;
+}
+template int batch_blocks<double>(int, int, int);
+template int batch_blocks<float>(int, int, int);
+
+hipError_t launch_plan_batch(Ctrl *const *ctrls, const PlanArgs *pa, int n, int mode, double t_end,
+                             int set_tend, hipStream_t st) {
+  hipLaunchKernelGGL(k_plan_batch, dim3((n + 63) / 64), dim3(64), 0, st, ctrls, pa, n, mode, t_end,
+                     set_tend);
+  return hipGetLastError();
+}
+
+template hipError_t launch_batch_stage<double>(int, int, const Scen<double> *, const void *, int,
+                                               const Consts &, int, int, int, hipStream_t);
+template hipError_t launch_batch_stage<float>(int, int, const Scen<float> *, const void *, int,
+                                              const Consts &, int, int, int, hipStream_t);
 template hipError_t launch_stage<double>(int, int, const Scen<double> &, const Consts &,
                                          const Launch &, hipStream_t);
 template hipError_t launch_stage<float>(int, int, const Scen<float> &, const Consts &,

@@ -76,6 +76,16 @@ _SIGS = {
     "dg2_autotune": (c_int32, [c_void_p, c_double, POINTER(c_int32)]),
     "dg2_state_layout": (c_int32, [c_void_p, POINTER(c_size_t), POINTER(c_size_t)]),
     "dg2_bind_device_state": (c_int32, [c_void_p, c_void_p, c_size_t]),
+    "dg2_batch_create": (c_int32, [POINTER(c_void_p), c_int32, c_void_p, POINTER(c_void_p)]),
+    "dg2_batch_destroy": (None, [c_void_p]),
+    "dg2_batch_last_error": (ctypes.c_char_p, [c_void_p]),
+    "dg2_batch_refresh": (c_int32, [c_void_p]),
+    "dg2_batch_set_launch": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
+    "dg2_batch_autotune": (c_int32, [c_void_p, c_double, POINTER(c_int32)]),
+    "dg2_batch_step": (c_int32, [c_void_p, c_int32]),
+    "dg2_batch_run_to": (c_int32, [c_void_p, c_double]),
+    "dg2_batch_sync": (c_int32, [c_void_p]),
+    "dg2_batch_time_steps": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
 }
 
 _lib = None
@@ -270,6 +280,68 @@ class Sim:
 
     def bind_device_state(self, ptr: Optional[int], nbytes: int = 0):
         self._check(self._lib.dg2_bind_device_state(self._ctx, ptr, nbytes))
+
+
+class Batch:
+    """Batched ensemble of ``Sim`` members advanced together (``dg2_batch``).
+
+    The members stay owned by the caller and must outlive the batch; step them
+    only through it, and call ``sync`` before reading a member.
+    """
+
+    def __init__(self, members: Sequence[Sim], stream=None):
+        self._lib = load_library()
+        self._b = c_void_p()
+        self.members = list(members)
+        if stream == "torch":
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        arr = (c_void_p * len(self.members))(*[m._ctx.value for m in self.members])
+        st = self._lib.dg2_batch_create(arr, len(self.members), stream, byref(self._b))
+        if st != 0:
+            msg = self._lib.dg2_batch_last_error(None)
+            raise DG2Error(st, msg.decode() if msg else "")
+
+    def _check(self, st: int):
+        if st != 0:
+            msg = self._lib.dg2_batch_last_error(self._b)
+            raise DG2Error(st, msg.decode() if msg else "")
+
+    def close(self):
+        if self._b:
+            self._lib.dg2_batch_destroy(self._b)
+            self._b = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def refresh(self):
+        self._check(self._lib.dg2_batch_refresh(self._b))
+
+    def set_launch(self, rows_per_wave: int = 0, waves_per_block: int = 4, graph_steps: int = 16):
+        self._check(self._lib.dg2_batch_set_launch(self._b, rows_per_wave, waves_per_block, graph_steps))
+
+    def autotune(self, budget_ms: float = 500.0) -> int:
+        r = c_int32()
+        self._check(self._lib.dg2_batch_autotune(self._b, budget_ms, byref(r)))
+        return r.value
+
+    def step(self, nsteps: int = 1):
+        self._check(self._lib.dg2_batch_step(self._b, nsteps))
+
+    def run_to(self, T: float):
+        self._check(self._lib.dg2_batch_run_to(self._b, T))
+
+    def sync(self):
+        self._check(self._lib.dg2_batch_sync(self._b))
+
+    def time_steps(self, nsteps: int) -> float:
+        ms = c_double()
+        self._check(self._lib.dg2_batch_time_steps(self._b, nsteps, byref(ms)))
+        return ms.value
 
 
 def sim_from_scenario(sc, stream=None, precision: Optional[str] = None,
