@@ -89,6 +89,47 @@ def cpu_baseline(sc, budget_s=15.0):
                       "after one warm-up step" % (w, w, sc.name, steps)}
 
 
+def ensemble_leg(count=256, steps=200, plain_steps=100, warmup=5):
+    """Batched ensemble against the plain per-scenario solver on the same GPU.
+
+    The 256-member ensemble (uneven grids 64..512 x 64..256, dx = 2 m, FP32,
+    each with its own device time step) is advanced by one persistent launch
+    per stage replayed from a graph, then the same scenarios are stepped one
+    after the other with the single-scenario path.  Both are reported as
+    element-stage updates/s.
+    """
+    import torch
+
+    from paper_2010_02003_amd import dg2
+    from paper_2010_02003_amd import workloads as WL
+
+    scs = WL.ensemble(count)
+    cells = sum(sc.cells for sc in scs)
+    sims = [dg2.sim_from_scenario(sc) for sc in scs]
+    batch = dg2.Batch(sims)
+    rows = batch.autotune(300.0)
+    batch.step(warmup)
+    batch.sync()
+    ms = batch.time_steps(steps)
+    batched = cells * 2 / (ms * 1e-3)
+    batch.close()
+    # plain: the same scenarios, one after the other, eager launches
+    t0 = time.perf_counter()
+    for s in sims:
+        s.step(plain_steps)
+    for s in sims:
+        s.sync()
+    torch.cuda.synchronize()
+    plain_wall = time.perf_counter() - t0
+    plain = cells * 2 * plain_steps / plain_wall
+    for s in sims:
+        s.close()
+    return {"scenarios": count, "cells": cells, "rows_per_wave": rows, "steps": steps,
+            "ms_per_step": ms, "value": batched, "plain_value": plain,
+            "plain_steps": plain_steps, "speedup_vs_plain": batched / plain,
+            "unit": "element-stage updates/s", "dtype": "f32"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +137,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="urban")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--rows", type=int, default=0, help="rows per wavefront (0: built-in)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed region, copy this many MiB three times with a plain "
@@ -176,6 +218,8 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         out["copy_calibration_mib"] = args.copy_mib
+    if not args.no_ensemble:
+        out["batched"] = ensemble_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc)
     print(json.dumps(out), flush=True)
