@@ -22,6 +22,10 @@ industry-standard finite volume models"):
   Sec. 2.1.3, Eq. (6)-(7)   optional local slope limiting (DG2-LL)
   Eq. (11)-(12)             mass and energy diagnostics
 
+For the adjoint, ``gauge_misfit_reference`` differentiates a gauge misfit
+through this same step with torch's reverse-mode automatic differentiation
+(Manning field and inflow hydrograph samples as parameters, fixed dt).
+
 Readings taken where the paper is silent or ambiguous (the same ones the HIP
 library implements):
 
@@ -316,7 +320,7 @@ def spatial_operator(W: torch.Tensor, bed: Bed, prm: Params, t_stage: float) -> 
         a, b = bc.first, bc.last + 1
         width = (b - a) * (dy if bc.side in (WEST, EAST) else dx)
         q_in = Q / width
-        if float(q_in) == 0.0:
+        if float(q_in.detach()) == 0.0:
             continue
         if bc.side == WEST:
             f = inflow_face_flux(q_in, hsp[a:b, 0], g)
@@ -663,3 +667,38 @@ def to_planes(U: torch.Tensor) -> np.ndarray:
 def from_planes(P) -> torch.Tensor:
     P = _t(np.asarray(P))
     return P.reshape(3, 3, P.shape[-2], P.shape[-1]).clone()
+
+
+# ---------------------------------------------------------------------------
+# Reverse-mode reference for the adjoint (gradients of a gauge misfit)
+# ---------------------------------------------------------------------------
+
+def gauge_misfit_reference(U0: torch.Tensor, bed: Bed, prm: Params, manning: torch.Tensor,
+                           side: int, first: int, last: int, t_q: torch.Tensor, Q: torch.Tensor,
+                           dt: float, steps: int, gauges, target: torch.Tensor):
+    """Loss J = sum over steps n = 1..N and gauges g of (h_g(U^n) - target[n-1, g])^2
+    for a fixed step dt, and its gradients with respect to the per-cell
+    Manning field and the inflow hydrograph samples Q (at times t_q), by
+    reverse-mode automatic differentiation through the oracle's step.
+
+    Returns (J, dJ/dmanning, dJ/dQ) as float64 tensors.  Every step of the
+    forward map is the plain oracle step above; torch's autograd supplies the
+    exact reverse pass of that arithmetic (ties of min/max split the gradient
+    evenly, derivatives of branch decisions are zero).
+    """
+    n = manning.detach().clone().requires_grad_(True)
+    q = Q.detach().clone().requires_grad_(True)
+    p = Params(**{**prm.__dict__})
+    p.manning = n
+    p.inflows = [InflowBC(side, first, last, t_q.to(F64), q)]
+    p.fixed_dt = dt
+    U = U0.clone()
+    t = 0.0
+    J = torch.zeros((), dtype=F64)
+    for k in range(steps):
+        U = step(U, t, bed, p, dt)
+        t = t + dt
+        h = sample_gauges(U, bed, p, gauges)[:, 0]
+        J = J + ((h - target[k]) ** 2).sum()
+    J.backward()
+    return J.detach(), n.grad.detach().clone(), q.grad.detach().clone()
