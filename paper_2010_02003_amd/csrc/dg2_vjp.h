@@ -299,5 +299,302 @@ __host__ __device__ inline void fric_elem_vjp(const double *U, double n, double 
   }
 }
 
+
+// ---- wet/dry treatment at the end of a stage (reading R15) ------------------
+// Code of the decision taken on a stage output: 1 = dry (discharge modes set
+// to zero), 2 = partly wet (every slope mode set to zero), 0 = unchanged.
+// The adjoint of the treatment zeroes the same entries of the adjoint.
+__host__ __device__ inline void apply_mask(unsigned char m, double *v) {
+  if (m & 1u) {
+    for (int k = 3; k < 9; ++k) v[k] = 0.0;
+  }
+  if (m & 2u) {
+    v[1] = v[2] = v[4] = v[5] = v[7] = v[8] = 0.0;
+  }
+}
+
+// ---- the DG2 operator L of Eq. (4) at one stage -----------------------------
+// Everything the adjoint of L needs: the stage input X (the state L was
+// evaluated at), the adjoint of the stage output before its wet/dry
+// treatment together with the treatment's codes, and the problem data.
+struct OpAdj {
+  const double *X;            // 9 planes of P elements
+  const double *lam;          // 9 planes: adjoint of the stage output
+  const unsigned char *mask;  // wet/dry code per cell of the stage output (nullptr: none)
+  const double *z;            // bed modes z0, z1x, z1y (3 planes)
+  int nx, ny;
+  long long P;
+  double idx, idy, g, tol;
+  int seg_first[4], seg_last[4];  // inflow segment per side (first > last: none)
+  double q[4];                    // unit discharge per side at this stage time (0: wall)
+};
+
+// Adjoint of the operator at the stage input of cell c, from the adjoint of
+// the operator's output mu_c = mask_c(lam_c).
+__host__ __device__ inline void load_mu(const OpAdj &a, long long c, double *mu) {
+  for (int k = 0; k < 9; ++k) mu[k] = a.lam[k * a.P + c];
+  if (a.mask) apply_mask(a.mask[c], mu);
+}
+
+// Raw face limits of a planar element (Sec. 2.1.2) and their dummy values.
+struct Limits {
+  double r[4][3];  // raw (h, qx, qy) at E, W, N, S
+  double d[4][3];  // dummy (h*, u, v) at E, W, N, S
+};
+
+__host__ __device__ inline void limits(const double *X, double tol, Limits &L) {
+  const double sgn[4] = {1.0, -1.0, 1.0, -1.0};
+  for (int f = 0; f < 4; ++f) {
+    const int m = f < 2 ? 1 : 2;
+    L.r[f][0] = X[0] + sgn[f] * X[m];
+    L.r[f][1] = X[3] + sgn[f] * X[3 + m];
+    L.r[f][2] = X[6] + sgn[f] * X[6 + m];
+    dummy(L.r[f][0], L.r[f][1], L.r[f][2], tol, L.d[f][0], L.d[f][1], L.d[f][2]);
+  }
+}
+
+enum { kE = 0, kW = 1, kN = 2, kS = 3 };
+
+__host__ __device__ inline double relu_neg(double h) { return h < 0.0 ? -h : 0.0; }
+// d relu(-h)/dh with the subgradient -1 taken at h = 0
+__host__ __device__ inline double relu_neg_d(double h) { return h <= 0.0 ? -1.0 : 0.0; }
+
+__host__ __device__ inline void load9(const double *base, long long P, long long c, double *v) {
+  for (int k = 0; k < 9; ++k) v[k] = base[k * P + c];
+}
+
+// JT = (dL/dX)^T mu gathered at cell (i, j), where mu is the adjoint of L at
+// every cell (the operator of a cell depends on its own modes and on those of
+// its four neighbours through the face fluxes and the wall-revised bed).
+// lq[side] receives the adjoint of the unit discharge of an inflow face of
+// this cell on that side (0 when there is none).  Wall ghosts are mirror
+// images of the cell (Sec. 2.1.2 reading R11), so their dependence folds
+// back onto the cell; ghosts carry no operator of their own.
+__host__ __device__ inline void operator_vjp(const OpAdj &a, int i, int j, double *JT, double *lq) {
+  const long long P = a.P;
+  const long long c = (long long)j * a.nx + i;
+  const double g = a.g, tol = a.tol, idx = a.idx, idy = a.idy;
+  double X[9], mu[9];
+  load9(a.X, P, c, X);
+  load_mu(a, c, mu);
+  Limits Lc;
+  limits(X, tol, Lc);
+  for (int k = 0; k < 9; ++k) JT[k] = 0.0;
+  for (int s = 0; s < 4; ++s) lq[s] = 0.0;
+  // adjoints of the dummy values (h*, u, v) at each face, and of the raw depths
+  double ld[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double lr[4] = {0, 0, 0, 0};
+  const double *dE = Lc.d[kE], *dW = Lc.d[kW], *dN = Lc.d[kN], *dS = Lc.d[kS];
+
+  // bed revision of the neighbours that uses this cell's raw depth
+  double lzb_east = 0.0, lzb_north = 0.0;
+  double dWv, dSv;  // wall-revision depths of the west and south faces
+
+  // ---- east face -------------------------------------------------------
+  {
+    double lF[3], l[6];
+    for (int k = 0; k < 3; ++k) lF[k] = -idx * (mu[3 * k] + 3.0 * mu[3 * k + 1]);
+    if (i + 1 < a.nx) {
+      double Xb[9], mb[9];
+      load9(a.X, P, c + 1, Xb);
+      load_mu(a, c + 1, mb);
+      Limits Lb;
+      limits(Xb, tol, Lb);
+      for (int k = 0; k < 3; ++k) lF[k] += idx * (mb[3 * k] - 3.0 * mb[3 * k + 1]);
+      hll_vjp(dE[0], dE[1], dE[2], Lb.d[kW][0], Lb.d[kW][1], Lb.d[kW][2], g, tol, lF, l);
+      for (int k = 0; k < 3; ++k) ld[kE][k] += l[k];
+      const double A0 = 0.5 * (Lb.d[kE][0] + Lb.d[kW][0]), B0 = 0.5 * (Lb.d[kE][0] - Lb.d[kW][0]);
+      lzb_east = -2.0 * g * idx * (A0 * mb[3] + B0 * mb[4]);
+    } else if (a.q[1] != 0.0 && j >= a.seg_first[1] && j <= a.seg_last[1]) {
+      // east inflow: F = [-q, q^2/h_b + g h_b^2/2, 0]
+      double lqq, lh;
+      inflow_vjp(a.q[1], dE[0], g, -lF[0], lF[1], lqq, lh);
+      ld[kE][0] += lh;
+      lq[1] += lqq;
+    } else {
+      // wall: the ghost's west limit is (h*, -u, v) of this east limit
+      hll_vjp(dE[0], dE[1], dE[2], dE[0], -dE[1], dE[2], g, tol, lF, l);
+      ld[kE][0] += l[0] + l[3];
+      ld[kE][1] += l[1] - l[4];
+      ld[kE][2] += l[2] + l[5];
+    }
+  }
+  // ---- west face -------------------------------------------------------
+  {
+    double lF[3], l[6];
+    for (int k = 0; k < 3; ++k) lF[k] = idx * (mu[3 * k] - 3.0 * mu[3 * k + 1]);
+    if (i > 0) {
+      double Xa[9], ma[9];
+      load9(a.X, P, c - 1, Xa);
+      load_mu(a, c - 1, ma);
+      Limits La;
+      limits(Xa, tol, La);
+      for (int k = 0; k < 3; ++k) lF[k] -= idx * (ma[3 * k] + 3.0 * ma[3 * k + 1]);
+      hll_vjp(La.d[kE][0], La.d[kE][1], La.d[kE][2], dW[0], dW[1], dW[2], g, tol, lF, l);
+      for (int k = 0; k < 3; ++k) ld[kW][k] += l[3 + k];
+      dWv = relu_neg(La.r[kE][0]);
+    } else {
+      if (a.q[0] != 0.0 && j >= a.seg_first[0] && j <= a.seg_last[0]) {
+        double lqq, lh;
+        inflow_vjp(a.q[0], dW[0], g, lF[0], lF[1], lqq, lh);
+        ld[kW][0] += lh;
+        lq[0] += lqq;
+      } else {
+        hll_vjp(dW[0], -dW[1], dW[2], dW[0], dW[1], dW[2], g, tol, lF, l);
+        ld[kW][0] += l[3] + l[0];
+        ld[kW][1] += l[4] - l[1];
+        ld[kW][2] += l[5] + l[2];
+      }
+      dWv = relu_neg(Lc.r[kW][0]);  // the ghost's east depth is this west depth
+    }
+  }
+  // ---- north face: G = [mass, x-mom, y-mom], HLL in (h, v, u) order ---------
+  {
+    double lG[3], lF[3], l[6];
+    for (int k = 0; k < 3; ++k) lG[k] = -idy * (mu[3 * k] + 3.0 * mu[3 * k + 2]);
+    if (j + 1 < a.ny) {
+      double Xb[9], mb[9];
+      load9(a.X, P, c + a.nx, Xb);
+      load_mu(a, c + a.nx, mb);
+      Limits Lb;
+      limits(Xb, tol, Lb);
+      for (int k = 0; k < 3; ++k) lG[k] += idy * (mb[3 * k] - 3.0 * mb[3 * k + 2]);
+      lF[0] = lG[0]; lF[1] = lG[2]; lF[2] = lG[1];
+      hll_vjp(dN[0], dN[2], dN[1], Lb.d[kS][0], Lb.d[kS][2], Lb.d[kS][1], g, tol, lF, l);
+      ld[kN][0] += l[0];
+      ld[kN][2] += l[1];
+      ld[kN][1] += l[2];
+      const double C0 = 0.5 * (Lb.d[kN][0] + Lb.d[kS][0]), D0 = 0.5 * (Lb.d[kN][0] - Lb.d[kS][0]);
+      lzb_north = -2.0 * g * idy * (C0 * mb[6] + D0 * mb[8]);
+    } else if (a.q[3] != 0.0 && i >= a.seg_first[3] && i <= a.seg_last[3]) {
+      // north inflow: G = [-q, 0, q^2/h_b + g h_b^2/2]
+      double lqq, lh;
+      inflow_vjp(a.q[3], dN[0], g, -lG[0], lG[2], lqq, lh);
+      ld[kN][0] += lh;
+      lq[3] += lqq;
+    } else {
+      // wall: the ghost's south limit is (h*, -v, u) in (h, v, u) order
+      lF[0] = lG[0]; lF[1] = lG[2]; lF[2] = lG[1];
+      hll_vjp(dN[0], dN[2], dN[1], dN[0], -dN[2], dN[1], g, tol, lF, l);
+      ld[kN][0] += l[0] + l[3];
+      ld[kN][2] += l[1] - l[4];
+      ld[kN][1] += l[2] + l[5];
+    }
+  }
+  // ---- south face --------------------------------------------------------
+  {
+    double lG[3], lF[3], l[6];
+    for (int k = 0; k < 3; ++k) lG[k] = idy * (mu[3 * k] - 3.0 * mu[3 * k + 2]);
+    if (j > 0) {
+      double Xa[9], ma[9];
+      load9(a.X, P, c - a.nx, Xa);
+      load_mu(a, c - a.nx, ma);
+      Limits La;
+      limits(Xa, tol, La);
+      for (int k = 0; k < 3; ++k) lG[k] -= idy * (ma[3 * k] + 3.0 * ma[3 * k + 2]);
+      lF[0] = lG[0]; lF[1] = lG[2]; lF[2] = lG[1];
+      hll_vjp(La.d[kN][0], La.d[kN][2], La.d[kN][1], dS[0], dS[2], dS[1], g, tol, lF, l);
+      ld[kS][0] += l[3];
+      ld[kS][2] += l[4];
+      ld[kS][1] += l[5];
+      dSv = relu_neg(La.r[kN][0]);
+    } else {
+      if (a.q[2] != 0.0 && i >= a.seg_first[2] && i <= a.seg_last[2]) {
+        // south inflow: G = [q, 0, q^2/h_b + g h_b^2/2]
+        double lqq, lh;
+        inflow_vjp(a.q[2], dS[0], g, lG[0], lG[2], lqq, lh);
+        ld[kS][0] += lh;
+        lq[2] += lqq;
+      } else {
+        lF[0] = lG[0]; lF[1] = lG[2]; lF[2] = lG[1];
+        hll_vjp(dS[0], -dS[2], dS[1], dS[0], dS[2], dS[1], g, tol, lF, l);
+        ld[kS][0] += l[3] + l[0];
+        ld[kS][2] += l[4] - l[1];
+        ld[kS][1] += l[5] + l[2];
+      }
+      dSv = relu_neg(Lc.r[kS][0]);
+    }
+  }
+
+  // ---- the cell's own terms: Gauss-point fluxes and bed source ------------
+  const double is3 = kIs3;
+  const double E[3] = {dE[0], dE[0] * dE[1], dE[0] * dE[2]};
+  const double Wc[3] = {dW[0], dW[0] * dW[1], dW[0] * dW[2]};
+  const double N[3] = {dN[0], dN[0] * dN[1], dN[0] * dN[2]};
+  const double S[3] = {dS[0], dS[0] * dS[1], dS[0] * dS[2]};
+  double A[3], B[3], C[3], D[3];
+  for (int k = 0; k < 3; ++k) {
+    A[k] = 0.5 * (E[k] + Wc[k]);
+    B[k] = 0.5 * (E[k] - Wc[k]);
+    C[k] = 0.5 * (N[k] + S[k]);
+    D[k] = 0.5 * (N[k] - S[k]);
+  }
+  const double zbx = a.z[P + c] - 0.5 * relu_neg(Lc.r[kE][0]) + 0.5 * dWv;
+  const double zby = a.z[2 * P + c] - 0.5 * relu_neg(Lc.r[kN][0]) + 0.5 * dSv;
+  double lA[3] = {0, 0, 0}, lB[3] = {0, 0, 0}, lC[3] = {0, 0, 0}, lD[3] = {0, 0, 0};
+  {
+    const double lF[3] = {3.0 * idx * mu[1], 3.0 * idx * mu[4], 3.0 * idx * mu[7]};
+    for (int p = 0; p < 2; ++p) {
+      const double o = p == 0 ? is3 : -is3;
+      double lh, lqx, lqy;
+      gflux_vjp(A[0] + o * B[0], A[1] + o * B[1], A[2] + o * B[2], g, tol, lF, lh, lqx, lqy);
+      lA[0] += lh; lA[1] += lqx; lA[2] += lqy;
+      lB[0] += o * lh; lB[1] += o * lqx; lB[2] += o * lqy;
+    }
+  }
+  {
+    // y Gauss flux [mass, x-mom, y-mom] is the normal flux of (h, qy, qx) reordered
+    const double lG[3] = {3.0 * idy * mu[2], 3.0 * idy * mu[5], 3.0 * idy * mu[8]};
+    const double lF[3] = {lG[0], lG[2], lG[1]};
+    for (int p = 0; p < 2; ++p) {
+      const double o = p == 0 ? is3 : -is3;
+      double lh, lqy, lqx;
+      gflux_vjp(C[0] + o * D[0], C[2] + o * D[2], C[1] + o * D[1], g, tol, lF, lh, lqy, lqx);
+      lC[0] += lh; lC[1] += lqx; lC[2] += lqy;
+      lD[0] += o * lh; lD[1] += o * lqx; lD[2] += o * lqy;
+    }
+  }
+  // bed source: L0 of qx has -2g A0 zbx/dx, L1x of qx has -2g B0 zbx/dx (and y alike)
+  lA[0] += -2.0 * g * idx * zbx * mu[3];
+  lB[0] += -2.0 * g * idx * zbx * mu[4];
+  lC[0] += -2.0 * g * idy * zby * mu[6];
+  lD[0] += -2.0 * g * idy * zby * mu[8];
+  const double lzbx = -2.0 * g * idx * (A[0] * mu[3] + B[0] * mu[4]);
+  const double lzby = -2.0 * g * idy * (C[0] * mu[6] + D[0] * mu[8]);
+  // zbx = z1x - relu(-h_E)/2 + relu(-h_W of the west neighbour or wall ghost)/2
+  lr[kE] += (-0.5 * lzbx + 0.5 * lzb_east) * relu_neg_d(Lc.r[kE][0]);
+  lr[kN] += (-0.5 * lzby + 0.5 * lzb_north) * relu_neg_d(Lc.r[kN][0]);
+  if (i == 0) lr[kW] += 0.5 * lzbx * relu_neg_d(Lc.r[kW][0]);
+  if (j == 0) lr[kS] += 0.5 * lzby * relu_neg_d(Lc.r[kS][0]);
+  // dummy modes of Eq. (5) from the conserved dummy limits (h*, h* u, h* v)
+  double lcons[4][3];
+  for (int k = 0; k < 3; ++k) {
+    lcons[kE][k] = 0.5 * (lA[k] + lB[k]);
+    lcons[kW][k] = 0.5 * (lA[k] - lB[k]);
+    lcons[kN][k] = 0.5 * (lC[k] + lD[k]);
+    lcons[kS][k] = 0.5 * (lC[k] - lD[k]);
+  }
+  const double *dd[4] = {dE, dW, dN, dS};
+  for (int f = 0; f < 4; ++f) {
+    ld[f][0] += lcons[f][0] + dd[f][1] * lcons[f][1] + dd[f][2] * lcons[f][2];
+    ld[f][1] += dd[f][0] * lcons[f][1];
+    ld[f][2] += dd[f][0] * lcons[f][2];
+  }
+  // dummy limits -> raw limits -> modes
+  const double sgn[4] = {1.0, -1.0, 1.0, -1.0};
+  for (int f = 0; f < 4; ++f) {
+    double rh, rqx, rqy;
+    dummy_vjp(Lc.r[f][0], Lc.r[f][1], Lc.r[f][2], tol, ld[f][0], ld[f][1], ld[f][2], rh, rqx, rqy);
+    rh += lr[f];
+    const int m = f < 2 ? 1 : 2;
+    JT[0] += rh;
+    JT[m] += sgn[f] * rh;
+    JT[3] += rqx;
+    JT[3 + m] += sgn[f] * rqx;
+    JT[6] += rqy;
+    JT[6 + m] += sgn[f] * rqy;
+  }
+}
+
 }  // namespace adj
 }  // namespace dg2
