@@ -265,6 +265,55 @@ dg2_status dg2_batch_sync(dg2_batch *b);
  * the average milliseconds per step (all members). */
 dg2_status dg2_batch_time_steps(dg2_batch *b, int32_t nsteps, double *ms_per_step);
 
+
+/* ------------------------------------------------------------------------
+ * Adjoint (reverse mode) of the DG2-NL step.  For a fixed step size, the
+ * forward run records the depth h at every gauge after each of `steps`
+ * steps; the backward run takes the gradient of any scalar loss with respect
+ * to those depths and returns the gradient with respect to the per-cell
+ * Manning coefficients n (Sec. 2.1.3 friction) and to the samples Q of one
+ * inflow hydrograph (the control side).  The step is differentiated as the
+ * library computes it: HLL flux, dummy limits and wall-revised bed of
+ * Sec. 2.1.2, RK2 stages, friction split and the end-of-stage wet/dry
+ * treatment (which passes no derivative through its decisions).  Where a
+ * min/max has equal arguments each receives half; the celerity sqrt(g h) has
+ * derivative 0 at h = 0.  Checkpoints of the state are kept every
+ * `checkpoint_every` steps and each segment is recomputed once during the
+ * backward run.
+ * ------------------------------------------------------------------------ */
+typedef struct dg2_adj dg2_adj;
+
+/* Bind an adjoint to ctx (FP64, DG2_NL, fixed dt > 0 set, >= 1 gauge).  The
+ * context's current state and time are the initial condition U^0; the
+ * control side (DG2_WEST..DG2_NORTH, or -1 for none) must have an inflow
+ * segment and hydrograph, whose sample times are read now.  ctx must
+ * outlive the adjoint; device memory: about (steps/K + 2K + 5) states of
+ * 9 nx ny doubles.  Errors: DG2_EINVAL, DG2_EUNSUPPORTED (FP32 or DG2-LL),
+ * DG2_ESTATE (no fixed dt, no gauges, no hydrograph), DG2_ENOMEM. */
+dg2_status dg2_adj_create(dg2_ctx *ctx, int32_t steps, int32_t checkpoint_every,
+                          int32_t control_side, dg2_adj **out);
+
+void dg2_adj_destroy(dg2_adj *adj);
+
+/* Message of the last failing call on adj (NULL: last dg2_adj_create failure). */
+const char *dg2_adj_last_error(const dg2_adj *adj);
+
+/* Forward run from U^0.  n_cell (ny*nx, row-major, >= 0; NULL: keep the
+ * context's Manning values) and Q (one value per hydrograph sample of the
+ * control side, >= 0; NULL: keep) are written into the context first.
+ * gauge_h (may be NULL) receives h[steps][ng]: the depth of the planar
+ * solution at each gauge after each step.  Returns when done. */
+dg2_status dg2_adj_forward(dg2_adj *adj, const double *n_cell, const double *Q, double *gauge_h);
+
+/* Backward run for the last forward run.  dL_dh[steps][ng]: gradient of the
+ * loss with respect to gauge_h.  grad_n (ny*nx, may be NULL) receives dL/dn
+ * per cell; grad_Q (one per hydrograph sample, may be NULL) dL/dQ.  The
+ * state adjoint is reduced in a fixed order: results are reproducible. */
+dg2_status dg2_adj_backward(dg2_adj *adj, const double *dL_dh, double *grad_n, double *grad_Q);
+
+/* Device milliseconds of the last forward and backward run (HIP events). */
+dg2_status dg2_adj_timing(const dg2_adj *adj, double *ms_forward, double *ms_backward);
+
 #ifdef __cplusplus
 }
 #endif

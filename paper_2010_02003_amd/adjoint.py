@@ -1,0 +1,38 @@
+"""torch.autograd binding of the library's adjoint step (``dg2_adj_*``).
+
+``GaugeDepths.apply(n_cell, Q, adj)`` runs the forward simulation in the
+HIP library and returns the gauge depths h[steps, ng] as a float64 tensor;
+its backward hands dL/dh to the library's reverse pass and returns dL/dn_cell
+and dL/dQ.  Any loss built from h with torch operations (a gauge misfit, a
+peak, a weighted sum) differentiates through it; parameter maps such as
+per-block Manning values expanded to cells are ordinary torch operations in
+front of it.  Argument marshalling only: all arithmetic of the step and of
+its adjoint runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .dg2 import Adjoint
+
+__all__ = ["GaugeDepths", "Adjoint"]
+
+
+class GaugeDepths(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, n_cell: torch.Tensor, Q: torch.Tensor, adj: Adjoint) -> torch.Tensor:
+        n = n_cell.detach().to("cpu", torch.float64).numpy()
+        q = Q.detach().to("cpu", torch.float64).numpy() if Q is not None else None
+        h = adj.forward(n, q)
+        ctx.adj = adj
+        ctx.devices = (n_cell.device, n_cell.dtype, None if Q is None else (Q.device, Q.dtype))
+        return torch.from_numpy(h).to(n_cell.device)
+
+    @staticmethod
+    def backward(ctx, grad_h: torch.Tensor):
+        gn, gq = ctx.adj.backward(grad_h.detach().to("cpu", torch.float64).numpy())
+        dev, dt, qinfo = ctx.devices
+        gn_t = torch.from_numpy(np.ascontiguousarray(gn)).to(dev, dt)
+        gq_t = None if qinfo is None else torch.from_numpy(gq).to(*qinfo)
+        return gn_t, gq_t, None

@@ -3,7 +3,8 @@
     python -m paper_2010_02003_amd.build
 
 Compiles the kernels and the C-ABI runtime in one hipcc invocation.  Packed
-FP32 instruction forms are disabled for the device code.
+FP32 instruction forms are disabled for the device code, and multiply-adds
+are contracted only within one expression.
 """
 import os
 import subprocess
@@ -13,12 +14,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdg2.so")
-SOURCES = ["dg2_kernels.hip", "dg2_api.hip"]
+SOURCES = ["dg2_kernels.hip", "dg2_api.hip", "dg2_adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
 def flags():
-    return ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # -ffp-contract=on: a*b+c is fused only within one source expression, so
+    # every inlined copy of a formula rounds alike and results do not depend
+    # on the launch shape (hipcc's default lets the backend fuse across
+    # statements differently in different copies).
+    return ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

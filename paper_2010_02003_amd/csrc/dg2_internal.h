@@ -14,6 +14,8 @@ struct Scen {
   const real *U;    // 9 planes: state at the start of the step
   real *U1;         // 9 planes: stage-1 result
   real *W1;         // 9 planes: limited stage-1 input (DG2-LL only)
+  real *Uout;       // 9 planes: stage-2 result (== U: in place)
+  unsigned char *mask;  // wet/dry code of each stage result (DG2-NL), or nullptr
   const real *z;    // 3 planes: z0, z1x, z1y
   const real *n;    // per-cell Manning or nullptr
   real n_uniform;

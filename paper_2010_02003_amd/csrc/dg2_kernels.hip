@@ -11,8 +11,10 @@
 // evaluated once, nothing goes through LDS, and each state plane is read
 // once per stage with unit-stride, wave-wide loads (structure of arrays).
 //
-// Stage 2 writes U^{n+1} in place over U^n: a lane reads U^n only at the
-// cell it writes, and halo lanes read only the stage-1 planes.  Its tail
+// Stage 2 writes U^{n+1} in place over U^n (or into a separate buffer): a
+// lane reads U^n only at the cell it writes, and halo lanes read only the
+// stage-1 planes.  On request the NL stages also store the wet/dry decision
+// of every result cell, which the adjoint step needs.  Its tail
 // folds the Courant candidate of every new cell into a wave minimum and one
 // atomic per wavefront; a single-thread plan kernel then turns the minimum
 // into the next step size on the device, so queued steps never wait for
@@ -267,7 +269,7 @@ __device__ __forceinline__ void march_nl(const Scen<real> &s, const Consts &c, i
   const real rain = (real)s.ctrl->rain;
   const real gdt = g * dt;
   const real *src = STAGE == 1 ? s.U : s.U1;
-  real *dst = STAGE == 1 ? s.U1 : const_cast<real *>(s.U);
+  real *dst = STAGE == 1 ? s.U1 : s.Uout;
 
   const int si = STAGE - 1;
   const real qW = (real)s.ctrl->qin[0][si], qE = (real)s.ctrl->qin[1][si];
@@ -343,10 +345,11 @@ __device__ __forceinline__ void march_nl(const Scen<real> &s, const Consts &c, i
 #pragma unroll
         for (int k = 0; k < 9; ++k) o[k] = half * (W1[k] + cur.W[k] + dt * Lop[k]);
       }
-      wet_dry_fix(o, tol);
+      const unsigned code = wet_dry_fix(o, tol);
       const unsigned off = (unsigned)cidx * (unsigned)sizeof(real);
 #pragma unroll
       for (int k = 0; k < 9; ++k) st_at(dst + k * s.P, off, o[k]);
+      if (s.mask) s.mask[cidx] = (unsigned char)code;
 
       if (STAGE == 2) new_state_checks(s, o, cidx, gmask, gslot, g, tol, mloc, flags);
     }
@@ -514,7 +517,7 @@ __device__ __forceinline__ void march_ll(const Scen<real> &s, const Consts &c, i
   const real rain = (real)s.ctrl->rain;
   const real gdt = g * dt;
   const real *src = STAGE == 1 ? s.U : s.U1;
-  real *dst = STAGE == 1 ? s.U1 : const_cast<real *>(s.U);
+  real *dst = STAGE == 1 ? s.U1 : s.Uout;
 
   const int si = STAGE - 1;
   const real qW = (real)s.ctrl->qin[0][si], qE = (real)s.ctrl->qin[1][si];

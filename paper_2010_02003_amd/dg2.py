@@ -86,6 +86,12 @@ _SIGS = {
     "dg2_batch_run_to": (c_int32, [c_void_p, c_double]),
     "dg2_batch_sync": (c_int32, [c_void_p]),
     "dg2_batch_time_steps": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
+    "dg2_adj_create": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_void_p)]),
+    "dg2_adj_destroy": (None, [c_void_p]),
+    "dg2_adj_last_error": (ctypes.c_char_p, [c_void_p]),
+    "dg2_adj_forward": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
+    "dg2_adj_backward": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
+    "dg2_adj_timing": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double)]),
 }
 
 _lib = None
@@ -342,6 +348,66 @@ class Batch:
         ms = c_double()
         self._check(self._lib.dg2_batch_time_steps(self._b, nsteps, byref(ms)))
         return ms.value
+
+
+class Adjoint:
+    """Reverse-mode driver of a ``Sim`` (``dg2_adj``): gauge depths after each
+    of ``steps`` fixed-size steps from the Sim's current state, and the
+    gradients of a loss on them with respect to the per-cell Manning field and
+    the samples of the control side's hydrograph.  The Sim must outlive it."""
+
+    def __init__(self, sim: Sim, steps: int, checkpoint_every: int = 100,
+                 control_side: int = -1, n_hydrograph: int = 0):
+        self._lib = load_library()
+        self.sim = sim
+        self.steps = steps
+        self.ng = sim.ng
+        self.n_hydrograph = n_hydrograph
+        self._a = c_void_p()
+        st = self._lib.dg2_adj_create(sim._ctx, steps, checkpoint_every, control_side, byref(self._a))
+        if st != 0:
+            msg = self._lib.dg2_adj_last_error(None)
+            raise DG2Error(st, msg.decode() if msg else "")
+
+    def _check(self, st: int):
+        if st != 0:
+            msg = self._lib.dg2_adj_last_error(self._a)
+            raise DG2Error(st, msg.decode() if msg else "")
+
+    def close(self):
+        if self._a:
+            self._lib.dg2_adj_destroy(self._a)
+            self._a = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, n_cell=None, Q=None) -> np.ndarray:
+        n = None if n_cell is None else _f64(n_cell)
+        if n is not None:
+            assert n.shape == (self.sim.ny, self.sim.nx)
+        q = None if Q is None else _f64(Q)
+        if q is not None:
+            assert q.shape == (self.n_hydrograph,)
+        h = np.empty((self.steps, self.ng), dtype=np.float64)
+        self._check(self._lib.dg2_adj_forward(self._a, _dp(n), _dp(q), _dp(h)))
+        return h
+
+    def backward(self, dL_dh):
+        d = _f64(dL_dh)
+        assert d.shape == (self.steps, self.ng)
+        gn = np.empty((self.sim.ny, self.sim.nx), dtype=np.float64)
+        gq = np.empty(max(self.n_hydrograph, 1), dtype=np.float64)
+        self._check(self._lib.dg2_adj_backward(self._a, _dp(d), _dp(gn), _dp(gq)))
+        return gn, gq[:self.n_hydrograph]
+
+    def timing(self):
+        f, b = c_double(), c_double()
+        self._check(self._lib.dg2_adj_timing(self._a, byref(f), byref(b)))
+        return f.value, b.value
 
 
 def sim_from_scenario(sc, stream=None, precision: Optional[str] = None,

@@ -247,7 +247,7 @@ def ensemble(count: int = 256, seed: int = 4) -> List[Scenario]:
 
 
 def adjoint_case(n: int = 512, dx: float = 2.0, seed: int = 5, steps: int = 2000,
-                 block: int = 64, nsamples: int = 60) -> Dict[str, object]:
+                 block: int = 64, nsamples: int = 60, dt: float = 0.05) -> Dict[str, object]:
     """Inputs of the gradient (adjoint) workload, 512 x 512 cells, dx = 2 m.
 
     Bed: fBm (seed, relief 5 m) plus a 3 m Gaussian bump (sigma 100 m) in the
@@ -255,8 +255,10 @@ def adjoint_case(n: int = 512, dx: float = 2.0, seed: int = 5, steps: int = 2000
     (fully wet).  Target Manning field: 8 x 8 blocks of 64 x 64 cells with
     n ~ U[0.02, 0.06]; the model starts from n = 0.04.  West-edge inflow over
     20 m centred on the edge, hydrograph given by ``nsamples`` samples evenly
-    spread over the run (target: triangular, peak 20 m^3/s; model start: 0.8 x
-    target).  Eight gauges at (64 + 128 k m, 512 m), k = 0..7.
+    spread over the run T = steps dt (target: triangular, 0 at t = 0, peak
+    20 m^3/s at T/3, 0 from 2T/3 on; model start: 0.8 x target).  Fixed step
+    dt = 0.05 s (Courant number about 0.24 at the deepest point).  Eight
+    gauges at ((k + 1/2) L/8, L/2), k = 0..7 (L = n dx; 64 + 128 k m, 512 m).
     """
     rng = np.random.default_rng(seed)
     X, Y = corner_xy(n, n, dx, dx)
@@ -267,10 +269,13 @@ def adjoint_case(n: int = 512, dx: float = 2.0, seed: int = 5, steps: int = 2000
     nb = n // block
     n_blocks_target = rng.uniform(0.02, 0.06, size=(nb, nb))
     mid = n // 2
-    gauges = np.stack([64.0 + 128.0 * np.arange(8), np.full(8, 512.0)], axis=1)
+    gauges = np.stack([(np.arange(8) + 0.5) * (L / 8.0), np.full(8, 0.5 * L)], axis=1)
+    T = steps * dt
+    t_q = np.linspace(0.0, T, nsamples)
+    Q_target = np.interp(t_q, [0.0, T / 3.0, 2.0 * T / 3.0, T], [0.0, 20.0, 0.0, 0.0])
     return dict(n=n, dx=dx, Z=Z, eta=eta, block=block, n_blocks_target=n_blocks_target,
-                n_model=0.04, steps=steps, nsamples=nsamples, inflow_side=WEST,
-                inflow_first=mid - 5, inflow_last=mid + 4, peak_target=20.0,
+                n_model=0.04, steps=steps, dt=dt, nsamples=nsamples, inflow_side=WEST,
+                inflow_first=mid - 5, inflow_last=mid + 4, t_q=t_q, Q_target=Q_target,
                 model_scale=0.8, gauges=gauges, checkpoint_every=100)
 
 
