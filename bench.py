@@ -2,6 +2,11 @@
 
     python bench.py [--steps K] [--warmup W] [--workload urban|floodplain|dambreak]
 
+Also reported: a batched-ensemble leg (256 uneven FP32 scenarios advanced
+together against the plain solver stepping them one by one) and an adjoint
+leg (gradient of a gauge misfit on a 512 x 512 FP64 domain, 2000 steps,
+against the plain forward run of those steps).
+
 Default workload: the urban-like domain, 4096 x 4096 cells, dx = 0.5 m, from
 dry under 50 mm/h rain, Manning 0.02 on streets and 0.05 elsewhere, FP32,
 DG2-NL, 2000 steps: the configuration whose working set (>1 GB) exceeds the
@@ -29,9 +34,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
 def kernel_source_hash() -> str:
+    """Hash of the stage kernels' sources and build flags (traffic counters
+    recorded for another hash are stale)."""
     h = hashlib.sha256()
-    for f in ("dg2_device.h", "dg2_kernels.hip", "dg2_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2010_02003_amd", "csrc", f), "rb").read())
+    pkg = os.path.join(ROOT, "paper_2010_02003_amd")
+    for f in ("csrc/dg2_device.h", "csrc/dg2_kernels.hip", "csrc/dg2_internal.h", "build.py"):
+        h.update(open(os.path.join(pkg, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -130,6 +138,69 @@ def ensemble_leg(count=256, steps=200, plain_steps=100, warmup=5):
             "unit": "element-stage updates/s", "dtype": "f32"}
 
 
+def adjoint_leg():
+    """Gradient of a gauge misfit on the 512 x 512 adjoint workload (FP64,
+    DG2-NL, 2000 steps of 0.05 s, checkpoints every 100 steps) against the
+    plain forward run of the same 2000 steps.
+
+    The gradient evaluation is one forward run (gauge record and
+    checkpoints) plus one backward run (segment recompute and the reverse
+    steps); both are timed with HIP events inside the library.  The loss is
+    the squared misfit to the gauge record of the target parameters.
+    """
+    import torch
+
+    from paper_2010_02003_amd import dg2
+    from paper_2010_02003_amd import workloads as WL
+
+    c = WL.adjoint_case()
+    n, nb, steps = c["n"], c["block"], c["steps"]
+    man = np.kron(np.full_like(c["n_blocks_target"], c["n_model"]), np.ones((nb, nb)))
+    man_t = np.kron(c["n_blocks_target"], np.ones((nb, nb)))
+    Q = c["Q_target"] * c["model_scale"]
+
+    def make_sim():
+        s = dg2.Sim(n, n, c["dx"], c["dx"])
+        s.set_dem_corners(c["Z"])
+        s.set_manning(man)
+        s.set_boundary(c["inflow_side"], dg2.BC_INFLOW_Q, c["inflow_first"], c["inflow_last"])
+        s.set_inflow_hydrograph(c["inflow_side"], c["t_q"], Q)
+        s.set_fixed_dt(c["dt"])
+        s.set_initial_corners(c["eta"], True)
+        s.set_gauges(c["gauges"], capacity=steps)
+        return s
+
+    plain = make_sim()
+    plain.step(20)
+    plain.sync()
+    plain.set_initial_corners(c["eta"], True)
+    _, _, ms_step = plain.time_kernels(steps)
+    plain_ms = ms_step * steps
+    plain.close()
+
+    s = make_sim()
+    adj = dg2.Adjoint(s, steps, c["checkpoint_every"], c["inflow_side"], len(c["t_q"]))
+    target = adj.forward(man_t, c["Q_target"])
+    h = adj.forward(man, Q)
+    adj.backward(2.0 * (h - target))  # warm-up
+    h = adj.forward(man, Q)
+    gn, gq = adj.backward(2.0 * (h - target))
+    fwd_ms, bwd_ms = adj.timing()
+    torch.cuda.synchronize()
+    adj.close()
+    s.close()
+    cells = n * n
+    grad_ms = fwd_ms + bwd_ms
+    return {"workload": "adjoint_512x512", "cells": cells, "steps": steps,
+            "checkpoint_every": c["checkpoint_every"], "dtype": "f64", "variant": "DG2-NL",
+            "plain_ms": plain_ms, "forward_ms": fwd_ms, "backward_ms": bwd_ms,
+            "gradient_ms": grad_ms, "gradient_vs_plain": grad_ms / plain_ms,
+            "value": cells * 2 * steps / (grad_ms * 1e-3), "plain_value": cells * 2 * steps / (plain_ms * 1e-3),
+            "unit": "element-stage updates/s (of the differentiated forward run)",
+            "loss": float(((h - target) ** 2).sum()), "grad_n_max": float(np.abs(gn).max()),
+            "grad_Q_max": float(np.abs(gq).max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +209,7 @@ def main():
     ap.add_argument("--workload", default="urban")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
     ap.add_argument("--rows", type=int, default=0, help="rows per wavefront (0: built-in)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed region, copy this many MiB three times with a plain "
@@ -220,6 +292,8 @@ def main():
         out["copy_calibration_mib"] = args.copy_mib
     if not args.no_ensemble:
         out["batched"] = ensemble_leg()
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc)
     print(json.dumps(out), flush=True)
