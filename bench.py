@@ -171,6 +171,7 @@ def adjoint_leg():
         return s
 
     plain = make_sim()
+    rows = plain.autotune(300.0)
     plain.step(20)
     plain.sync()
     plain.set_initial_corners(c["eta"], True)
@@ -179,6 +180,7 @@ def adjoint_leg():
     plain.close()
 
     s = make_sim()
+    s.set_launch(rows, 4)
     adj = dg2.Adjoint(s, steps, c["checkpoint_every"], c["inflow_side"], len(c["t_q"]))
     target = adj.forward(man_t, c["Q_target"])
     h = adj.forward(man, Q)
@@ -193,6 +195,7 @@ def adjoint_leg():
     grad_ms = fwd_ms + bwd_ms
     return {"workload": "adjoint_512x512", "cells": cells, "steps": steps,
             "checkpoint_every": c["checkpoint_every"], "dtype": "f64", "variant": "DG2-NL",
+            "rows_per_wave": rows,
             "plain_ms": plain_ms, "forward_ms": fwd_ms, "backward_ms": bwd_ms,
             "gradient_ms": grad_ms, "gradient_vs_plain": grad_ms / plain_ms,
             "value": cells * 2 * steps / (grad_ms * 1e-3), "plain_value": cells * 2 * steps / (plain_ms * 1e-3),
@@ -210,6 +213,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
+    ap.add_argument("--leg", choices=["adjoint", "ensemble"], default=None,
+                    help="run only this leg and print its JSON (for profiling)")
     ap.add_argument("--rows", type=int, default=0, help="rows per wavefront (0: built-in)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed region, copy this many MiB three times with a plain "
@@ -227,6 +232,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the MI355X"
     torch.cuda.set_device(0)
+    if args.leg:
+        print(json.dumps(adjoint_leg() if args.leg == "adjoint" else ensemble_leg()), flush=True)
+        return
     sc = make_workload(args.workload)
     esz = 4 if sc.precision == "fp32" else 8
     sim = dg2.sim_from_scenario(sc, stream="torch")

@@ -16,7 +16,7 @@ import torch
 
 from .dg2 import Adjoint
 
-__all__ = ["GaugeDepths", "Adjoint"]
+__all__ = ["GaugeDepths", "DG2Loss", "Adjoint"]
 
 
 class GaugeDepths(torch.autograd.Function):
@@ -36,3 +36,36 @@ class GaugeDepths(torch.autograd.Function):
         gn_t = torch.from_numpy(np.ascontiguousarray(gn)).to(dev, dt)
         gq_t = None if qinfo is None else torch.from_numpy(gq).to(*qinfo)
         return gn_t, gq_t, None
+
+
+class DG2Loss(torch.autograd.Function):
+    """Gauge misfit J = sum over steps and gauges of (h - target)^2 as a
+    function of per-block Manning values and the hydrograph samples.
+
+    ``DG2Loss.apply(n_blocks, Q, adj, target, block)``: ``n_blocks`` of shape
+    (ny / block, nx / block) is expanded to cells (each block of block x
+    block cells shares one value), the library's forward run gives h, and
+    the backward run gives dJ/dn per cell, summed back over each block.
+    """
+
+    @staticmethod
+    def forward(ctx, n_blocks: torch.Tensor, Q: torch.Tensor, adj: Adjoint, target, block: int):
+        nb = n_blocks.detach().to("cpu", torch.float64).numpy()
+        n_cell = np.kron(nb, np.ones((block, block)))
+        q = Q.detach().to("cpu", torch.float64).numpy()
+        h = adj.forward(n_cell, q)
+        tgt = np.asarray(target.detach().cpu() if torch.is_tensor(target) else target, dtype=np.float64)
+        r = h - tgt
+        ctx.adj, ctx.block, ctx.r = adj, block, r
+        ctx.meta = (n_blocks.device, n_blocks.dtype, Q.device, Q.dtype, nb.shape)
+        return torch.tensor(float((r * r).sum()), dtype=n_blocks.dtype, device=n_blocks.device)
+
+    @staticmethod
+    def backward(ctx, grad_J: torch.Tensor):
+        g = float(grad_J)
+        gn, gq = ctx.adj.backward(2.0 * g * ctx.r)
+        dev, dt, qdev, qdt, (by, bx) = ctx.meta
+        b = ctx.block
+        gblocks = gn.reshape(by, b, bx, b).sum(axis=(1, 3))
+        return (torch.from_numpy(gblocks).to(dev, dt), torch.from_numpy(gq).to(qdev, qdt),
+                None, None, None)

@@ -213,6 +213,7 @@ struct dg2_adj {
   double *g_buf = nullptr, *g_t = nullptr;  // forward gauge record
   bool forward_done = false;
   double t0 = 0.0;
+  long long step0 = 0;  // the context's step count at U^0
   double ms_fwd = 0.0, ms_bwd = 0.0;
   std::string err;
 };
@@ -430,6 +431,7 @@ dg2_status dg2_adj_create(dg2_ctx *c, int32_t steps, int32_t every, int32_t side
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return bail(ahip(a, e, "adjoint setup"));
   a->t0 = h.t;
+  a->step0 = h.step;
   *out = a;
   return DG2_OK;
 }
@@ -511,14 +513,18 @@ dg2_status dg2_adj_backward(dg2_adj *a, const double *dL_dh, double *grad_n, dou
   hipLaunchKernelGGL(k_adj_init, dim3(1024), dim3(256), 0, st, G, a->lam, a->gn,
                      (const double *)(a->seed + (size_t)(N - 1) * ng));
   ACHK(a, hipGetLastError(), "adjoint init");
-  const PlanArgs pa = fwd_plan(a, false);
+  // the planner records each recomputed step's plan in ctrlseg
+  PlanArgs pa = fwd_plan(a, false);
+  pa.hist = a->ctrlseg;
+  pa.hist_len = K;
   for (int sg = a->nseg - 1; sg >= 0; --sg) {
     const int n0 = sg * K, len = (N - n0) < K ? (N - n0) : K;
     // recompute the segment, keeping every step
     ACHK(a, hipMemcpyAsync(a->Useg, state(a->ckpt, a, sg), a->sb, hipMemcpyDeviceToDevice, st), "restore");
     ACHK(a, hipMemcpyAsync(a->actrl, a->ckctrl + sg, sizeof(Ctrl), hipMemcpyDeviceToDevice, st), "restore");
+    ACHK(a, hipMemcpyAsync(a->ctrlseg, a->ckctrl + sg, sizeof(Ctrl), hipMemcpyDeviceToDevice, st), "restore");
+    pa.hist_base = a->step0 + n0;
     for (int m = 0; m < len; ++m) {
-      ACHK(a, hipMemcpyAsync(a->ctrlseg + m, a->actrl, sizeof(Ctrl), hipMemcpyDeviceToDevice, st), "record");
       const Scen<double> s1 = fwd_scen(a, state(a->Useg, a, m), state(a->U1seg, a, m), nullptr,
                                        a->mseg + (size_t)(2 * m) * P, false);
       const Scen<double> s2 = fwd_scen(a, state(a->Useg, a, m), state(a->U1seg, a, m),

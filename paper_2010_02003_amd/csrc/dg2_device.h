@@ -30,6 +30,7 @@ struct Ctrl {
   unsigned int flags;  // bit 0: NaN, bit 1: negative mean depth
   unsigned int pad;
   long long gauge_written;  // samples recorded since the gauge record was reset
+  int hyd_k[4];        // per side: hydrograph interval of the last lookup (search hint)
 };
 
 enum : unsigned { kFlagNaN = 1u, kFlagNegative = 2u };
@@ -45,6 +46,11 @@ struct PlanArgs {
   int ng;          // gauges (for the time record)
   int gauge_cap;
   double *gauge_t;
+  // optional record of each planned step: hist[step - hist_base] = Ctrl
+  // for 0 <= step - hist_base < hist_len (the adjoint's segment recompute)
+  Ctrl *hist;
+  long long hist_base;
+  int hist_len;
 };
 
 // Arithmetic kernels by precision.  FP64 keeps correctly rounded division,

@@ -657,10 +657,13 @@ __global__ void __launch_bounds__(256) k_batch_stage(const Scen<real> *__restric
 // rain depth and stage inflows.
 // ---------------------------------------------------------------------------
 
-__device__ double hydrograph_at(int n, const double *t, const double *Q, double x) {
+// Piecewise-linear hydrograph value at time x, held constant outside the
+// samples.  k is the interval of a previous lookup at an earlier or equal
+// time (the planner's times only grow); the scan continues from there.
+__device__ double hydrograph_at(int n, const double *t, const double *Q, double x, int &k) {
   if (x <= t[0]) return Q[0];
   if (x >= t[n - 1]) return Q[n - 1];
-  int k = 0;
+  if (k < 0 || k > n - 2 || !(t[k] <= x)) k = 0;
   while (k + 1 < n && t[k + 1] <= x) ++k;
   const double w = (x - t[k]) / (t[k + 1] - t[k]);
   return Q[k] * (1.0 - w) + Q[k + 1] * w;
@@ -676,8 +679,11 @@ __device__ void plan_next(Ctrl *c, const PlanArgs &p) {
                               : 0.0;
   for (int sd = 0; sd < 4; ++sd) {
     if (p.nhyd[sd] > 0) {
-      c->qin[sd][0] = hydrograph_at(p.nhyd[sd], p.hyd_t[sd], p.hyd_Q[sd], t) / p.seg_len[sd];
-      c->qin[sd][1] = hydrograph_at(p.nhyd[sd], p.hyd_t[sd], p.hyd_Q[sd], t + dt) / p.seg_len[sd];
+      int k = c->hyd_k[sd];
+      c->qin[sd][0] = hydrograph_at(p.nhyd[sd], p.hyd_t[sd], p.hyd_Q[sd], t, k) / p.seg_len[sd];
+      const int k0 = k;
+      c->qin[sd][1] = hydrograph_at(p.nhyd[sd], p.hyd_t[sd], p.hyd_Q[sd], t + dt, k) / p.seg_len[sd];
+      c->hyd_k[sd] = k0;
     } else {
       c->qin[sd][0] = 0.0;
       c->qin[sd][1] = 0.0;
@@ -706,6 +712,10 @@ __device__ void plan_step(Ctrl *c, const PlanArgs &p, int mode, double t_end, in
     c->minbits = kInfBits;
   }
   plan_next(c, p);
+  if (p.hist) {
+    const long long m = c->step - p.hist_base;
+    if (m >= 0 && m < p.hist_len) p.hist[m] = *c;
+  }
 }
 
 __global__ void k_plan(Ctrl *c, PlanArgs p, int mode, double t_end, int set_tend) {

@@ -27,8 +27,9 @@ __host__ __device__ inline void dummy(double h, double qn, double qt, double tol
                                       double &un, double &ut) {
   hs = h > 0.0 ? h : 0.0;
   if (h > tol) {
-    un = qn / h;
-    ut = qt / h;
+    const double r = 1.0 / h;
+    un = qn * r;
+    ut = qt * r;
   } else {
     un = 0.0;
     ut = 0.0;
@@ -42,10 +43,11 @@ __host__ __device__ inline void dummy_vjp(double h, double qn, double qt, double
   lqn = 0.0;
   lqt = 0.0;
   if (h > tol) {
-    const double un = qn / h, ut = qt / h;
-    lqn = lun / h;
-    lqt = lut / h;
-    lh += -(un * lun + ut * lut) / h;
+    const double r = 1.0 / h;
+    const double un = qn * r, ut = qt * r;
+    lqn = lun * r;
+    lqt = lut * r;
+    lh += -(un * lun + ut * lut) * r;
   }
 }
 
@@ -90,8 +92,8 @@ __host__ __device__ inline void hll(double hL, double uL, double vL, double hR, 
     for (int k = 0; k < 3; ++k) F[k] = FR[k];
   } else {
     const double UL[3] = {hL, hL * uL, hL * vL}, UR[3] = {hR, hR * uR, hR * vR};
-    const double D = sR - sL;
-    for (int k = 0; k < 3; ++k) F[k] = (sR * FL[k] - sL * FR[k] + sL * sR * (UR[k] - UL[k])) / D;
+    const double iD = 1.0 / (sR - sL);
+    for (int k = 0; k < 3; ++k) F[k] = (sR * FL[k] - sL * FR[k] + sL * sR * (UR[k] - UL[k])) * iD;
   }
 }
 
@@ -120,16 +122,17 @@ __host__ __device__ inline void hll_vjp(double hL, double uL, double vL, double 
     for (int k = 0; k < 3; ++k) lFR[k] = lF[k];
   } else {
     const double UL[3] = {hL, hL * uL, hL * vL}, UR[3] = {hR, hR * uR, hR * vR};
-    const double D = sR - sL;
+    const double iD = 1.0 / (sR - sL);
     for (int k = 0; k < 3; ++k) {
       const double dU = UR[k] - UL[k];
-      const double Fk = (sR * FL[k] - sL * FR[k] + sL * sR * dU) / D;
-      lFL[k] = lF[k] * sR / D;
-      lFR[k] = -lF[k] * sL / D;
-      lUR[k] = lF[k] * sL * sR / D;
+      const double Fk = (sR * FL[k] - sL * FR[k] + sL * sR * dU) * iD;
+      const double l = lF[k] * iD;
+      lFL[k] = l * sR;
+      lFR[k] = -l * sL;
+      lUR[k] = l * sL * sR;
       lUL[k] = -lUR[k];
-      lsL += lF[k] * (-FR[k] + sR * dU + Fk) / D;
-      lsR += lF[k] * (FL[k] + sL * dU - Fk) / D;
+      lsL += l * (-FR[k] + sR * dU + Fk);
+      lsR += l * (FL[k] + sL * dU - Fk);
     }
   }
   // wave speeds -> (uL, uR, cL, cR)
@@ -203,8 +206,9 @@ __host__ __device__ inline void inflow_vjp(double q, double h_in, double g, doub
                                            double &lq, double &lh_in) {
   const double hc = cbrt(q * q / g);
   const double hb = dmax(h_in, hc);
-  const double lhb = lF1 * (-q * q / (hb * hb) + g * hb);
-  lq = lF0 + lF1 * 2.0 * q / hb;
+  const double rb = 1.0 / hb;
+  const double lhb = lF1 * (-q * q * rb * rb + g * hb);
+  lq = lF0 + lF1 * 2.0 * q * rb;
   lh_in = max_vjp_a(h_in, hc) * lhb;
   if (q != 0.0) lq += max_vjp_a(hc, h_in) * lhb * (2.0 / 3.0) * hc / q;
 }
@@ -240,10 +244,11 @@ __host__ __device__ inline void fric_point_vjp(double h, double qx, double qy, d
   const double f = a / (1.0 + a);
   const double dfda = 1.0 / ((1.0 + a) * (1.0 + a));
   const double S = -(ldx * qx + ldy * qy) * dfda;  // adjoint of a
-  lqx = -ldx * f + S * a * qx / qq;
-  lqy = -ldy * f + S * a * qy / qq;
-  lh = S * a * (-7.0 / 3.0) / h;
-  ln = S * a * 2.0 / n;
+  const double Sa = S * a, Saq = Sa / qq;
+  lqx = -ldx * f + Saq * qx;
+  lqy = -ldy * f + Saq * qy;
+  lh = Sa * (-7.0 / 3.0) / h;
+  ln = Sa * 2.0 / n;
 }
 
 // Friction split of a planar element, forward: W[9] from U[9].
@@ -355,6 +360,18 @@ __host__ __device__ inline void limits(const double *X, double tol, Limits &L) {
 
 enum { kE = 0, kW = 1, kN = 2, kS = 3 };
 
+// One face limit of a planar element: raw (h, qx, qy) and dummy (h*, u, v).
+__host__ __device__ inline void face_limit(const double *X, int f, double tol, double *r, double *d) {
+  const double sg = (f == kE || f == kN) ? 1.0 : -1.0;
+  const int m = f < 2 ? 1 : 2;
+  r[0] = X[0] + sg * X[m];
+  r[1] = X[3] + sg * X[3 + m];
+  r[2] = X[6] + sg * X[6 + m];
+  dummy(r[0], r[1], r[2], tol, d[0], d[1], d[2]);
+}
+
+__host__ __device__ inline double hstar(double h) { return h > 0.0 ? h : 0.0; }
+
 __host__ __device__ inline double relu_neg(double h) { return h < 0.0 ? -h : 0.0; }
 // d relu(-h)/dh with the subgradient -1 taken at h = 0
 __host__ __device__ inline double relu_neg_d(double h) { return h <= 0.0 ? -1.0 : 0.0; }
@@ -395,15 +412,15 @@ __host__ __device__ inline void operator_vjp(const OpAdj &a, int i, int j, doubl
     double lF[3], l[6];
     for (int k = 0; k < 3; ++k) lF[k] = -idx * (mu[3 * k] + 3.0 * mu[3 * k + 1]);
     if (i + 1 < a.nx) {
-      double Xb[9], mb[9];
+      double Xb[9], mb[9], rb[3], db[3];
       load9(a.X, P, c + 1, Xb);
       load_mu(a, c + 1, mb);
-      Limits Lb;
-      limits(Xb, tol, Lb);
+      face_limit(Xb, kW, tol, rb, db);
       for (int k = 0; k < 3; ++k) lF[k] += idx * (mb[3 * k] - 3.0 * mb[3 * k + 1]);
-      hll_vjp(dE[0], dE[1], dE[2], Lb.d[kW][0], Lb.d[kW][1], Lb.d[kW][2], g, tol, lF, l);
+      hll_vjp(dE[0], dE[1], dE[2], db[0], db[1], db[2], g, tol, lF, l);
       for (int k = 0; k < 3; ++k) ld[kE][k] += l[k];
-      const double A0 = 0.5 * (Lb.d[kE][0] + Lb.d[kW][0]), B0 = 0.5 * (Lb.d[kE][0] - Lb.d[kW][0]);
+      const double ehb = hstar(Xb[0] + Xb[1]);
+      const double A0 = 0.5 * (ehb + db[0]), B0 = 0.5 * (ehb - db[0]);
       lzb_east = -2.0 * g * idx * (A0 * mb[3] + B0 * mb[4]);
     } else if (a.q[1] != 0.0 && j >= a.seg_first[1] && j <= a.seg_last[1]) {
       // east inflow: F = [-q, q^2/h_b + g h_b^2/2, 0]
@@ -424,15 +441,14 @@ __host__ __device__ inline void operator_vjp(const OpAdj &a, int i, int j, doubl
     double lF[3], l[6];
     for (int k = 0; k < 3; ++k) lF[k] = idx * (mu[3 * k] - 3.0 * mu[3 * k + 1]);
     if (i > 0) {
-      double Xa[9], ma[9];
+      double Xa[9], ma[9], ra[3], da[3];
       load9(a.X, P, c - 1, Xa);
       load_mu(a, c - 1, ma);
-      Limits La;
-      limits(Xa, tol, La);
+      face_limit(Xa, kE, tol, ra, da);
       for (int k = 0; k < 3; ++k) lF[k] -= idx * (ma[3 * k] + 3.0 * ma[3 * k + 1]);
-      hll_vjp(La.d[kE][0], La.d[kE][1], La.d[kE][2], dW[0], dW[1], dW[2], g, tol, lF, l);
+      hll_vjp(da[0], da[1], da[2], dW[0], dW[1], dW[2], g, tol, lF, l);
       for (int k = 0; k < 3; ++k) ld[kW][k] += l[3 + k];
-      dWv = relu_neg(La.r[kE][0]);
+      dWv = relu_neg(ra[0]);
     } else {
       if (a.q[0] != 0.0 && j >= a.seg_first[0] && j <= a.seg_last[0]) {
         double lqq, lh;
@@ -453,18 +469,18 @@ __host__ __device__ inline void operator_vjp(const OpAdj &a, int i, int j, doubl
     double lG[3], lF[3], l[6];
     for (int k = 0; k < 3; ++k) lG[k] = -idy * (mu[3 * k] + 3.0 * mu[3 * k + 2]);
     if (j + 1 < a.ny) {
-      double Xb[9], mb[9];
+      double Xb[9], mb[9], rb[3], db[3];
       load9(a.X, P, c + a.nx, Xb);
       load_mu(a, c + a.nx, mb);
-      Limits Lb;
-      limits(Xb, tol, Lb);
+      face_limit(Xb, kS, tol, rb, db);
       for (int k = 0; k < 3; ++k) lG[k] += idy * (mb[3 * k] - 3.0 * mb[3 * k + 2]);
       lF[0] = lG[0]; lF[1] = lG[2]; lF[2] = lG[1];
-      hll_vjp(dN[0], dN[2], dN[1], Lb.d[kS][0], Lb.d[kS][2], Lb.d[kS][1], g, tol, lF, l);
+      hll_vjp(dN[0], dN[2], dN[1], db[0], db[2], db[1], g, tol, lF, l);
       ld[kN][0] += l[0];
       ld[kN][2] += l[1];
       ld[kN][1] += l[2];
-      const double C0 = 0.5 * (Lb.d[kN][0] + Lb.d[kS][0]), D0 = 0.5 * (Lb.d[kN][0] - Lb.d[kS][0]);
+      const double nhb = hstar(Xb[0] + Xb[2]);
+      const double C0 = 0.5 * (nhb + db[0]), D0 = 0.5 * (nhb - db[0]);
       lzb_north = -2.0 * g * idy * (C0 * mb[6] + D0 * mb[8]);
     } else if (a.q[3] != 0.0 && i >= a.seg_first[3] && i <= a.seg_last[3]) {
       // north inflow: G = [-q, 0, q^2/h_b + g h_b^2/2]
@@ -486,18 +502,17 @@ __host__ __device__ inline void operator_vjp(const OpAdj &a, int i, int j, doubl
     double lG[3], lF[3], l[6];
     for (int k = 0; k < 3; ++k) lG[k] = idy * (mu[3 * k] - 3.0 * mu[3 * k + 2]);
     if (j > 0) {
-      double Xa[9], ma[9];
+      double Xa[9], ma[9], ra[3], da[3];
       load9(a.X, P, c - a.nx, Xa);
       load_mu(a, c - a.nx, ma);
-      Limits La;
-      limits(Xa, tol, La);
+      face_limit(Xa, kN, tol, ra, da);
       for (int k = 0; k < 3; ++k) lG[k] -= idy * (ma[3 * k] + 3.0 * ma[3 * k + 2]);
       lF[0] = lG[0]; lF[1] = lG[2]; lF[2] = lG[1];
-      hll_vjp(La.d[kN][0], La.d[kN][2], La.d[kN][1], dS[0], dS[2], dS[1], g, tol, lF, l);
+      hll_vjp(da[0], da[2], da[1], dS[0], dS[2], dS[1], g, tol, lF, l);
       ld[kS][0] += l[3];
       ld[kS][2] += l[4];
       ld[kS][1] += l[5];
-      dSv = relu_neg(La.r[kN][0]);
+      dSv = relu_neg(ra[0]);
     } else {
       if (a.q[2] != 0.0 && i >= a.seg_first[2] && i <= a.seg_last[2]) {
         // south inflow: G = [q, 0, q^2/h_b + g h_b^2/2]

@@ -156,7 +156,7 @@ def test_adjoint_full_size_workload_directional_derivatives():
 
 
 def test_torch_autograd_function_per_block_manning():
-    from paper_2010_02003_amd.adjoint import GaugeDepths
+    from paper_2010_02003_amd.adjoint import DG2Loss, GaugeDepths
 
     _say("torch autograd binding")
     c, _, Q, target = _case(64, 16, nsamples=5)
@@ -171,9 +171,17 @@ def test_torch_autograd_function_per_block_manning():
     man = n_cell.detach().numpy()
     Jr, gnr, gqr = _reference(c, man, Q, target)
     gblocks = gnr.reshape(4, nb, 4, nb).sum(axis=(1, 3))
-    assert float(loss) == pytest.approx(float(Jr), rel=1e-10)
+    assert float(loss.detach()) == pytest.approx(float(Jr), rel=1e-10)
     assert _rel(n_blocks.grad.numpy(), gblocks.numpy()) <= 1e-8
     assert _rel(q.grad.numpy(), gqr.numpy()) <= 1e-8
+    # the same loss through DG2Loss (block expansion and misfit inside)
+    nb2 = n_blocks.detach().clone().requires_grad_(True)
+    q2 = torch.tensor(Q, requires_grad=True)
+    J = DG2Loss.apply(nb2, q2, a, target, nb)
+    J.backward()
+    assert float(J.detach()) == pytest.approx(float(Jr), rel=1e-10)
+    assert _rel(nb2.grad.numpy(), gblocks.numpy()) <= 1e-8
+    assert _rel(q2.grad.numpy(), gqr.numpy()) <= 1e-8
     a.close()
     s.close()
 
