@@ -365,10 +365,31 @@ __device__ __forceinline__ void march_nl(const Scen<real> &s, const Consts &c, i
   if (STAGE == 2) publish_min(s, lane, mloc, flags);
 }
 
+// Work item of a wavefront.  Workgroups go to the 8 XCDs round-robin
+// (workgroup b on XCD b % 8); they are renumbered so that each XCD works
+// through one contiguous range of items, where neighbouring strips and row
+// segments share cache lines (strip edges, halo rows) in the same L2.
+// Stage 1 walks the items in the opposite order to stage 2, so that each
+// stage starts on the rows the previous one wrote last, which are still in
+// the Infinity Cache.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+  const int x = b & 7, k = b >> 3;
+  const int per = G >> 3, rem = G & 7;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+template <int STAGE>
+__device__ __forceinline__ int stage_item(const Launch &L, int &item) {
+  item = xcd_block(blockIdx.x, gridDim.x) * L.wpb + (threadIdx.x >> 6);
+  if (item >= L.nitems) return 0;
+  if (STAGE == 1) item = L.nitems - 1 - item;
+  return 1;
+}
+
 template <typename real, int STAGE>
 __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch L) {
-  const int item = blockIdx.x * L.wpb + (threadIdx.x >> 6);
-  if (item >= L.nitems) return;
+  int item;
+  if (!stage_item<STAGE>(L, item)) return;
   march_nl<real, STAGE>(s, c, item % L.nstrips, item / L.nstrips, L.R, threadIdx.x & 63);
 }
 
@@ -613,8 +634,8 @@ __device__ __forceinline__ void march_ll(const Scen<real> &s, const Consts &c, i
 
 template <typename real, int STAGE>
 __global__ void __launch_bounds__(256) k_stage_ll(Scen<real> s, Consts c, Launch L) {
-  const int item = blockIdx.x * L.wpb + (threadIdx.x >> 6);
-  if (item >= L.nitems) return;
+  int item;
+  if (!stage_item<STAGE>(L, item)) return;
   march_ll<real, STAGE>(s, c, item % L.nstrips, item / L.nstrips, L.R, threadIdx.x & 63);
 }
 
