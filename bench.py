@@ -68,8 +68,9 @@ def make_workload(name):
     raise SystemExit("unknown workload " + name)
 
 
-def cpu_baseline(sc, budget_s=15.0):
-    """The FP64 oracle, as it stands, on a corner window of the same workload."""
+def cpu_baseline(sc, budget_s=15.0, single_core_s=8.0):
+    """The FP64 oracle, as it stands, on a corner window of the same workload:
+    with torch's default thread count (the host's cores), then on one core."""
     import torch
 
     from oracle import dg2_oracle as O
@@ -83,18 +84,28 @@ def cpu_baseline(sc, budget_s=15.0):
         sub.manning = sc.manning[:w, :w]
     sub.inflows = [b for b in sc.inflows if (b.last < w)]
     U, bed, prm = O.setup(sub)
-    t0 = time.perf_counter()
-    r = O.run(U, bed, prm, steps=1)
-    one = time.perf_counter() - t0
-    steps = int(max(1, min(400, budget_s / max(one, 1e-3))))
-    t0 = time.perf_counter()
-    O.run(r.U, bed, prm, steps=steps, t0=r.t)
-    el = time.perf_counter() - t0
-    rate = w * w * 2 * steps / el
-    return {"value": rate, "unit": "element-stage updates/s", "cores": torch.get_num_threads(),
+
+    def rate(budget, cap):
+        t0 = time.perf_counter()
+        r = O.run(U, bed, prm, steps=1)
+        one = time.perf_counter() - t0
+        steps = int(max(1, min(cap, budget / max(one, 1e-3))))
+        t0 = time.perf_counter()
+        O.run(r.U, bed, prm, steps=steps, t0=r.t)
+        return w * w * 2 * steps / (time.perf_counter() - t0), steps
+
+    cores = torch.get_num_threads()
+    value, steps = rate(budget_s, 400)
+    torch.set_num_threads(1)
+    try:
+        single, steps1 = rate(single_core_s, 100)
+    finally:
+        torch.set_num_threads(cores)
+    return {"value": value, "unit": "element-stage updates/s", "cores": cores,
             "kind": "oracle",
             "sample": "%dx%d corner window of the %s workload, FP64 torch-CPU oracle, %d steps "
-                      "after one warm-up step" % (w, w, sc.name, steps)}
+                      "after one warm-up step" % (w, w, sc.name, steps),
+            "single_core": {"value": single, "cores": 1, "steps": steps1}}
 
 
 def ensemble_leg(count=256, steps=200, plain_steps=100, warmup=5):

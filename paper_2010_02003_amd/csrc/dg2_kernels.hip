@@ -247,15 +247,22 @@ __device__ __forceinline__ void load_own(const Scen<real> &s, long long cidx, Ow
   }
 }
 
-// Software-pipelined march: the loads of row j+2 are issued at the top of
-// iteration j and consumed one iteration later, so they have a whole row of
-// arithmetic to hide behind; a row's own data (bed slopes and, in stage 2,
-// U^n and n) is loaded at the top of its iteration, ahead of the flux
-// arithmetic of that row.  Prefetching the own data a row earlier as well
-// costs more registers than it gains.
-template <typename real, int STAGE>
-__device__ __forceinline__ void march_nl(const Scen<real> &s, const Consts &c, int strip, int seg,
-                                         int R, int lane) {
+// Software-pipelined march: the loads of the row after next are issued at
+// the top of each iteration and consumed one iteration later, so they have a
+// whole row of arithmetic to hide behind; a row's own data (bed slopes and,
+// in stage 2, U^n and n) is loaded at the top of its iteration, ahead of the
+// flux arithmetic of that row.  Prefetching the own data a row earlier as
+// well costs more registers than it gains.
+//
+// Even segments march up and odd segments march down, so two neighbouring
+// segments reach their common boundary at about the same time and each one's
+// halo row is still in L2 when the other reads it.  The face between two
+// rows is always y_face(lower, upper), so the direction changes no result.
+// The carried face (CF, dC) is the south face of the current row when
+// marching up and its north face when marching down.
+template <typename real, int STAGE, bool down>
+__device__ __forceinline__ void march_nl_dir(const Scen<real> &s, const Consts &c, int strip, int seg,
+                                             int R, int lane) {
   const double dtd = s.ctrl->dt;
   if (!(dtd > 0.0)) return;
 
@@ -263,6 +270,8 @@ __device__ __forceinline__ void march_nl(const Scen<real> &s, const Consts &c, i
   const real half = real(0.5);
   const int i = strip * kStripNL + lane - 1;
   const int j0 = seg * R, j1 = min(j0 + R, s.ny);
+  const int d = down ? -1 : 1;
+  const int jfirst = down ? j1 - 1 : j0, jstop = down ? j0 - 1 : j1;
   const bool own = lane >= 1 && lane <= kStripNL && i < s.nx;
   const int ci = i < 0 ? 0 : (i >= s.nx ? s.nx - 1 : i);
   const bool mx = (i < 0) || (i >= s.nx);
@@ -290,35 +299,55 @@ __device__ __forceinline__ void march_nl(const Scen<real> &s, const Consts &c, i
   Row<real> cur, nxt;
   Raw<real, STAGE> rawA, rawN;
   Own<real, STAGE> ownC;
-  real GS0, GS1, GS2, dS;
+  real CF0, CF1, CF2, dC;
   {
-    Row<real> prev;
-    load_raw<real, STAGE>(s, src, j0 - 1, ci, rawA);
-    load_raw<real, STAGE>(s, src, j0, ci, rawN);
-    build_row<real, STAGE>(rawA, j0 - 1, s.ny, mx, rain, gdt, tol, prev);
-    load_raw<real, STAGE>(s, src, j0 + 1, ci, rawA);
-    build_row<real, STAGE>(rawN, j0, s.ny, mx, rain, gdt, tol, cur);
-    y_face(prev, cur, g, tol, GS0, GS1, GS2);
-    dS = dmax(real(0), -prev.nr);
-    if (j0 == 0 && colS) {
-      inflow_flux(qS, cur.sh, g, GS0, GS2);
-      GS1 = real(0);
+    Row<real> back;
+    load_raw<real, STAGE>(s, src, jfirst - d, ci, rawA);
+    load_raw<real, STAGE>(s, src, jfirst, ci, rawN);
+    build_row<real, STAGE>(rawA, jfirst - d, s.ny, mx, rain, gdt, tol, back);
+    load_raw<real, STAGE>(s, src, jfirst + d, ci, rawA);
+    build_row<real, STAGE>(rawN, jfirst, s.ny, mx, rain, gdt, tol, cur);
+    if (!down) {
+      y_face(back, cur, g, tol, CF0, CF1, CF2);
+      dC = dmax(real(0), -back.nr);
+      if (jfirst == 0 && colS) {
+        inflow_flux(qS, cur.sh, g, CF0, CF2);
+        CF1 = real(0);
+      }
+    } else {
+      north_face(cur, back, jfirst == s.ny - 1 && colN, qN, g, tol, CF0, CF1, CF2, dC);
     }
   }
-  // rawA holds row j0+1
 
   double mloc = __longlong_as_double((long long)kInfBits);
   unsigned flags = 0;
 
-  for (int j = j0; j < j1; ++j) {
-    // prefetch: row j+2 and the own data of row j+1
-    if (j + 2 <= j1) load_raw<real, STAGE>(s, src, j + 2, ci, rawN);
+  for (int j = jfirst; j != jstop; j += d) {
+    // prefetch: the row after next, and the own data of this row
+    if (down ? (j - 2 >= j0 - 1) : (j + 2 <= j1)) load_raw<real, STAGE>(s, src, j + 2 * d, ci, rawN);
     if (own) load_own<real, STAGE>(s, (long long)j * s.nx + i, ownC);
 
-    build_row<real, STAGE>(rawA, j + 1, s.ny, mx, rain, gdt, tol, nxt);
+    build_row<real, STAGE>(rawA, j + d, s.ny, mx, rain, gdt, tol, nxt);
 
-    real GN0, GN1, GN2, dN;
-    north_face(cur, nxt, j == s.ny - 1 && colN, qN, g, tol, GN0, GN1, GN2, dN);
+    real GN0, GN1, GN2, dN, GS0, GS1, GS2, dS;
+    if (!down) {
+      north_face(cur, nxt, j == s.ny - 1 && colN, qN, g, tol, GN0, GN1, GN2, dN);
+      GS0 = CF0;
+      GS1 = CF1;
+      GS2 = CF2;
+      dS = dC;
+    } else {
+      y_face(nxt, cur, g, tol, GS0, GS1, GS2);
+      dS = dmax(real(0), -nxt.nr);
+      if (j == 0 && colS) {
+        inflow_flux(qS, cur.sh, g, GS0, GS2);
+        GS1 = real(0);
+      }
+      GN0 = CF0;
+      GN1 = CF1;
+      GN2 = CF2;
+      dN = dC;
+    }
     real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
     east_west_faces(cur, faceW && j >= s.seg_first[0] && j <= s.seg_last[0], qW,
                     faceE && j >= s.seg_first[1] && j <= s.seg_last[1], qE, g, tol, FE0, FE1, FE2,
@@ -356,13 +385,29 @@ __device__ __forceinline__ void march_nl(const Scen<real> &s, const Consts &c, i
 
     cur = nxt;
     rawA = rawN;
-    GS0 = GN0;
-    GS1 = GN1;
-    GS2 = GN2;
-    dS = dN;
+    if (!down) {
+      CF0 = GN0;
+      CF1 = GN1;
+      CF2 = GN2;
+      dC = dN;
+    } else {
+      CF0 = GS0;
+      CF1 = GS1;
+      CF2 = GS2;
+      dC = dS;
+    }
   }
 
   if (STAGE == 2) publish_min(s, lane, mloc, flags);
+}
+
+template <typename real, int STAGE>
+__device__ __forceinline__ void march_nl(const Scen<real> &s, const Consts &c, int strip, int seg,
+                                         int R, int lane) {
+  if (seg & 1)
+    march_nl_dir<real, STAGE, true>(s, c, strip, seg, R, lane);
+  else
+    march_nl_dir<real, STAGE, false>(s, c, strip, seg, R, lane);
 }
 
 // Work item of a wavefront.  Workgroups go to the 8 XCDs round-robin
@@ -861,9 +906,10 @@ Launch make_launch(int nx, int ny, int variant, int R, int wpb) {
   const int cols = variant == 1 ? kStripLL : kStripNL;
   L.nstrips = (nx + cols - 1) / cols;
   if (R <= 0) {
-    // aim at ~16k wavefronts: several rounds of the ~3-4k resident slots, so
-    // the last round is short, while the two halo rows stay a small share
-    long long r = (long long)L.nstrips * ny / 16384;
+    // aim at ~34k wavefronts: about ten rounds of the ~3k resident slots, so
+    // the last round is short; the halo rows are mostly L2 hits (the work
+    // items of one XCD are neighbours)
+    long long r = (long long)L.nstrips * ny / 34000;
     R = (int)(r < 4 ? 4 : (r > 32 ? 32 : r));
   }
   if (R > ny) R = ny;
