@@ -32,6 +32,20 @@ sys.path.insert(0, ROOT)
 METRIC = "DG2 element-stage updates/s + % HBM peak; batched & adjoint vs plain"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
+# Table 3 of the paper (Sec. 3.3): wall-clock seconds of DG2-NL and DG2-LL on
+# one core of a desktop computer (model not given), at the industrial models'
+# resolution.  Context only: the paper gives no cell or step counts for them.
+PAPER_RUNTIMES = {
+    "hardware": "one core of a desktop CPU (model not stated in the paper)",
+    "source": "Table 3, Sec. 3.3",
+    "DG2-NL_s": {"sloping topography, 20 h": 75, "multiple ponds, 48 h": 833,
+                 "obstruction, 15 min": 5.5, "rural catchment, 30 h": 12297,
+                 "oblique building, 2 min": 10363},
+    "DG2-LL_s": {"sloping topography, 20 h": 166, "multiple ponds, 48 h": 1734,
+                 "obstruction, 15 min": 12, "rural catchment, 30 h": 22260,
+                 "oblique building, 2 min": 15337},
+}
+
 
 def kernel_source_hash() -> str:
     """Hash of the stage kernels' sources and build flags (traffic counters
@@ -300,6 +314,7 @@ def main():
                                 "ms_per_launch": ms1},
                      "step_frac": cells * (b1 + b2) / (wall / args.steps) / 1e9 / HBM_PEAK_GBS},
         "cpu_baseline": None,
+        "paper_runtimes": PAPER_RUNTIMES,
     }
     if args.copy_mib > 0:
         n = args.copy_mib * (1 << 20) // 4
