@@ -66,6 +66,7 @@ class Scenario:
     theta: float = 10.0
     variant: str = "NL"  # "NL" or "LL"
     precision: str = "fp64"  # "fp64" or "fp32"
+    flux: str = "HLL"  # face flux: "HLL" or "ROE"
     steps: Optional[int] = None
     t_end: Optional[float] = None
     fixed_dt: float = 0.0
