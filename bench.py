@@ -307,7 +307,7 @@ def main():
         "config": {"workload": sc.name, "nx": sc.nx, "ny": sc.ny, "dx": sc.dx, "variant": "DG2-" + sc.variant,
                    "precision": sc.precision, "cells": cells, "sim_time_s": t_sim,
                    "last_dt_s": last_dt, "mass_m3": mass, "min_h0": hmin},
-        "roofline": {"bound": "hbm", "kernel": "stage 2 (k_stage_nl<%s,2>)" % ("float" if esz == 4 else "double"),
+        "roofline": {"bound": "hbm", "kernel": "stage 2 (k_stage_nl<%s, 2, HLL>)" % ("float" if esz == 4 else "double"),
                      "achieved": ach2, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach2 / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_cell": b2, "ms_per_launch": ms2,
                      "stage1": {"achieved": ach1, "frac": ach1 / HBM_PEAK_GBS, "bytes_per_cell": b1,

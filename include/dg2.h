@@ -70,6 +70,11 @@ typedef enum { DG2_WEST = 0, DG2_EAST = 1, DG2_SOUTH = 2, DG2_NORTH = 3 } dg2_si
 /* Boundary segments default to solid walls (mirror ghost cells).  An inflow
  * segment takes a discharge hydrograph (dg2_set_inflow_hydrograph). */
 typedef enum { DG2_BC_WALL = 0, DG2_BC_INFLOW_Q = 1 } dg2_bc;
+/* Two-argument face flux of Sec. 2.1.2.  DG2_FLUX_HLL (default): HLL with
+ * two-rarefaction wave-speed estimates and dry-bed front speeds.
+ * DG2_FLUX_ROE: Roe's solver, the paper's choice (Roe averages, no entropy
+ * fix), with the HLL flux at faces that have a side at or below tol_dry. */
+typedef enum { DG2_FLUX_HLL = 0, DG2_FLUX_ROE = 1 } dg2_flux;
 
 typedef struct {
   int32_t nx, ny;         /* cells in x and y, each >= 1                      */
@@ -83,6 +88,7 @@ typedef struct {
   double ll_threshold;    /* shock-detector threshold, default 10 (Eq. 6)     */
   double dt_max;          /* cap on the time step (s), default 1              */
   void *hip_stream;       /* borrowed hipStream_t; NULL: the library makes one */
+  int32_t flux;           /* dg2_flux, default DG2_FLUX_HLL                   */
 } dg2_config;
 
 /* Fill *cfg with the defaults above for an nx x ny grid of dx x dy cells

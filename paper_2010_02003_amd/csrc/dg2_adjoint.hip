@@ -357,8 +357,8 @@ dg2_status dg2_adj_create(dg2_ctx *c, int32_t steps, int32_t every, int32_t side
   if (!out) return afail(nullptr, DG2_EINVAL, "out is NULL");
   *out = nullptr;
   if (!c) return afail(nullptr, DG2_EINVAL, "ctx is NULL");
-  if (c->f32 || c->cfg.variant != DG2_NL)
-    return afail(nullptr, DG2_EUNSUPPORTED, "the adjoint step is FP64 DG2-NL only");
+  if (c->f32 || c->cfg.variant != DG2_NL || c->cfg.flux != DG2_FLUX_HLL)
+    return afail(nullptr, DG2_EUNSUPPORTED, "the adjoint step is FP64 DG2-NL with the HLL flux only");
   if (!(c->fixed_dt > 0)) return afail(nullptr, DG2_ESTATE, "the adjoint needs a fixed step size");
   if (c->ng < 1) return afail(nullptr, DG2_ESTATE, "the adjoint needs at least one gauge");
   if (steps < 1 || every < 1) return afail(nullptr, DG2_EINVAL, "steps and checkpoint interval must be >= 1");

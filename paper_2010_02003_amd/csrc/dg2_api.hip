@@ -220,6 +220,7 @@ dg2_status dg2_create(const dg2_config *cfg, dg2_ctx **out) {
     return fail(nullptr, DG2_EINVAL, "g, cfl, tol_dry, dt_max must be > 0 and ll_threshold >= 0");
   if (cfg->prec != DG2_FP64 && cfg->prec != DG2_FP32) return fail(nullptr, DG2_EINVAL, "bad prec");
   if (cfg->variant != DG2_NL && cfg->variant != DG2_LL) return fail(nullptr, DG2_EINVAL, "bad variant");
+  if (cfg->flux != DG2_FLUX_HLL && cfg->flux != DG2_FLUX_ROE) return fail(nullptr, DG2_EINVAL, "bad flux");
 
   dg2_ctx *c = new (std::nothrow) dg2_ctx();
   if (!c) return fail(nullptr, DG2_ENOMEM, "host allocation failed");
@@ -880,8 +881,11 @@ dg2_status batch_setup(dg2_batch *b) {
   dg2_status st = b->f32 ? upload_scens<float>(b) : upload_scens<double>(b);
   if (st != DG2_OK) return st;
   if ((st = build_items(b)) != DG2_OK) return st;
-  b->blocks1 = b->f32 ? batch_blocks<float>(1, b->variant, b->wpb) : batch_blocks<double>(1, b->variant, b->wpb);
-  b->blocks2 = b->f32 ? batch_blocks<float>(2, b->variant, b->wpb) : batch_blocks<double>(2, b->variant, b->wpb);
+  const int fx = b->consts.flux;
+  b->blocks1 = b->f32 ? batch_blocks<float>(1, b->variant, fx, b->wpb)
+                      : batch_blocks<double>(1, b->variant, fx, b->wpb);
+  b->blocks2 = b->f32 ? batch_blocks<float>(2, b->variant, fx, b->wpb)
+                      : batch_blocks<double>(2, b->variant, fx, b->wpb);
   const int need = (b->nitems + b->wpb - 1) / b->wpb;
   if (b->blocks1 > need) b->blocks1 = need;
   if (b->blocks2 > need) b->blocks2 = need;
@@ -916,9 +920,10 @@ dg2_status dg2_batch_create(dg2_ctx *const *members, int32_t n, void *hip_stream
   for (int k = 0; k < n; ++k) {
     const dg2_ctx *c = members[k];
     if (!c) return bfail(nullptr, DG2_EINVAL, "NULL member");
-    if (c->cfg.prec != c0->cfg.prec || c->cfg.variant != c0->cfg.variant || c->cfg.g != c0->cfg.g ||
+    if (c->cfg.prec != c0->cfg.prec || c->cfg.variant != c0->cfg.variant ||
+        c->cfg.flux != c0->cfg.flux || c->cfg.g != c0->cfg.g ||
         c->cfg.tol_dry != c0->cfg.tol_dry || c->cfg.ll_threshold != c0->cfg.ll_threshold)
-      return bfail(nullptr, DG2_EINVAL, "members differ in precision, variant, g, tol_dry or threshold");
+      return bfail(nullptr, DG2_EINVAL, "members differ in precision, variant, flux, g, tol_dry or threshold");
   }
   dg2_batch *b = new (std::nothrow) dg2_batch();
   if (!b) return bfail(nullptr, DG2_ENOMEM, "host allocation failed");

@@ -116,6 +116,7 @@ inline Consts consts(const dg2_ctx *c) {
   k.g = c->cfg.g;
   k.tol = c->cfg.tol_dry;
   k.theta = c->cfg.ll_threshold;
+  k.flux = c->cfg.flux;
   return k;
 }
 

@@ -144,6 +144,48 @@ __device__ __forceinline__ void hll(real hL, real uL, real vL, real hR, real uR,
   }
 }
 
+// Roe's approximate Riemann solver (the paper's choice, Sec. 2.1.2) on wet
+// dummy limits: Roe averages u = (sqrt(hL) uL + sqrt(hR) uR)/(sqrt(hL) +
+// sqrt(hR)) (v alike) and c = sqrt(g (hL + hR)/2), three waves with
+// eigenvalues u - c, u, u + c, no entropy fix:
+// F = (F_L + F_R)/2 - sum |lambda_k| alpha_k r_k / 2.  A face with a side at
+// or below the drying tolerance takes the HLL flux.
+template <typename real>
+__device__ __forceinline__ void roe(real hL, real uL, real vL, real hR, real uR, real vR, real g,
+                                    real tol, real &F0, real &F1, real &F2) {
+  if (!(hL > tol && hR > tol)) {
+    hll(hL, uL, vL, hR, uR, vR, g, tol, F0, F1, F2);
+    return;
+  }
+  const real rL = dsqrt(hL), rR = dsqrt(hR);
+  const real ir = drcp(rL + rR);
+  const real uh = (rL * uL + rR * uR) * ir, vh = (rL * vL + rR * vR) * ir;
+  const real ch = dsqrt(real(0.5) * g * (hL + hR));
+  const real qL = hL * uL, qR = hR * uR;
+  const real dh = hR - hL, dq = qR - qL, dr = hR * vR - hL * vL;
+  const real i2c = drcp(real(2) * ch);
+  const real l1 = uh - ch, l3 = uh + ch;
+  const real m1 = fabs(l1) * (((uh + ch) * dh - dq) * i2c);  // |lambda_1| alpha_1
+  const real m3 = fabs(l3) * ((dq - (uh - ch) * dh) * i2c);  // |lambda_3| alpha_3
+  const real m2 = fabs(uh) * (dr - vh * dh);                 // |lambda_2| alpha_2
+  const real FL1 = qL * uL + real(0.5) * g * hL * hL, FR1 = qR * uR + real(0.5) * g * hR * hR;
+  F0 = real(0.5) * ((qL + qR) - (m1 + m3));
+  F1 = real(0.5) * ((FL1 + FR1) - (m1 * l1 + m3 * l3));
+  F2 = real(0.5) * ((qL * vL + qR * vR) - ((m1 + m3) * vh + m2));
+}
+
+// The two-argument face flux, chosen at compile time.
+enum : int { kFluxHLL = 0, kFluxRoe = 1 };
+
+template <int FLUX, typename real>
+__device__ __forceinline__ void face_flux(real hL, real uL, real vL, real hR, real uR, real vR,
+                                          real g, real tol, real &F0, real &F1, real &F2) {
+  if (FLUX == kFluxRoe)
+    roe(hL, uL, vL, hR, uR, vR, g, tol, F0, F1, F2);
+  else
+    hll(hL, uL, vL, hR, uR, vR, g, tol, F0, F1, F2);
+}
+
 // Prescribed discharge q through an inflow face: normal flux components
 // [q, q^2/h_b + g h_b^2/2, 0], h_b = max(inner dummy depth, critical depth).
 template <typename real>

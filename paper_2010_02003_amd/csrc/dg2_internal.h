@@ -34,6 +34,7 @@ struct Scen {
 
 struct Consts {
   double g, tol, theta;
+  int flux;  // kFluxHLL or kFluxRoe
 };
 
 struct Launch {
@@ -74,7 +75,7 @@ hipError_t launch_plan_batch(Ctrl *const *ctrls, const PlanArgs *pa, int n, int 
 hipError_t launch_batch_status(Ctrl *const *ctrls, int n, unsigned *out, hipStream_t st);
 
 template <typename real>
-int batch_blocks(int stage, int variant, int wpb);
+int batch_blocks(int stage, int variant, int flux, int wpb);
 
 enum PlanMode { kPlanOnly = 0, kPlanFromMin = 1, kPlanFinishStep = 2 };
 

@@ -47,11 +47,11 @@ __device__ __forceinline__ void row_limits(Row<real> &r, real tol) {
 
 // Flux through the y-face between a lower row and the row above it, as
 // [mass, x-momentum, y-momentum].
-template <typename real>
+template <int FLUX, typename real>
 __device__ __forceinline__ void y_face(const Row<real> &lo, const Row<real> &hi, real g, real tol,
                                        real &G0, real &G1, real &G2) {
   real m, fn, ft;
-  hll(lo.nh, lo.nv, lo.nu, hi.sh, hi.sv, hi.su, g, tol, m, fn, ft);
+  face_flux<FLUX>(lo.nh, lo.nv, lo.nu, hi.sh, hi.sv, hi.su, g, tol, m, fn, ft);
   G0 = m;
   G1 = ft;
   G2 = fn;
@@ -97,11 +97,11 @@ __device__ __forceinline__ void cell_operator(const Row<real> &cur, real FE0, re
 // North face of a row (the y-face to the row above) as [mass, x-mom, y-mom];
 // an inflow segment on the north wall replaces the flux.  dN = max(0, -h_N^-)
 // for the wall revision of the bed at that face.
-template <typename real>
+template <int FLUX, typename real>
 __device__ __forceinline__ void north_face(const Row<real> &cur, const Row<real> &nxt, bool inflow,
                                            real q, real g, real tol, real &G0, real &G1, real &G2,
                                            real &dN) {
-  y_face(cur, nxt, g, tol, G0, G1, G2);
+  y_face<FLUX>(cur, nxt, g, tol, G0, G1, G2);
   dN = dmax(real(0), -cur.nr);
   if (inflow) {
     inflow_flux(q, cur.nh, g, G0, G2);
@@ -113,7 +113,7 @@ __device__ __forceinline__ void north_face(const Row<real> &cur, const Row<real>
 // East face of every lane's cell (with the '+' limit of the lane to the east)
 // and its west face (the east face of the lane to the west), with inflow
 // segments on the west and east walls, and the wall-revision depths.
-template <typename real>
+template <int FLUX, typename real>
 __device__ __forceinline__ void east_west_faces(const Row<real> &cur, bool inW, real qW, bool inE,
                                                 real qE, real g, real tol, real &FE0, real &FE1,
                                                 real &FE2, real &FW0, real &FW1, real &FW2,
@@ -121,7 +121,7 @@ __device__ __forceinline__ void east_west_faces(const Row<real> &cur, bool inW, 
   const real ph = __shfl_down(cur.wh, 1, 64);
   const real pu = __shfl_down(cur.wu, 1, 64);
   const real pv = __shfl_down(cur.wv, 1, 64);
-  hll(cur.eh, cur.eu, cur.ev, ph, pu, pv, g, tol, FE0, FE1, FE2);
+  face_flux<FLUX>(cur.eh, cur.eu, cur.ev, ph, pu, pv, g, tol, FE0, FE1, FE2);
   if (inW) {
     inflow_flux(qW, ph, g, FE0, FE1);
     FE2 = real(0);
@@ -260,7 +260,7 @@ __device__ __forceinline__ void load_own(const Scen<real> &s, long long cidx, Ow
 // rows is always y_face(lower, upper), so the direction changes no result.
 // The carried face (CF, dC) is the south face of the current row when
 // marching up and its north face when marching down.
-template <typename real, int STAGE, bool down>
+template <typename real, int STAGE, int FLUX, bool down>
 __device__ __forceinline__ void march_nl_dir(const Scen<real> &s, const Consts &c, int strip, int seg,
                                              int R, int lane) {
   const double dtd = s.ctrl->dt;
@@ -308,14 +308,14 @@ __device__ __forceinline__ void march_nl_dir(const Scen<real> &s, const Consts &
     load_raw<real, STAGE>(s, src, jfirst + d, ci, rawA);
     build_row<real, STAGE>(rawN, jfirst, s.ny, mx, rain, gdt, tol, cur);
     if (!down) {
-      y_face(back, cur, g, tol, CF0, CF1, CF2);
+      y_face<FLUX>(back, cur, g, tol, CF0, CF1, CF2);
       dC = dmax(real(0), -back.nr);
       if (jfirst == 0 && colS) {
         inflow_flux(qS, cur.sh, g, CF0, CF2);
         CF1 = real(0);
       }
     } else {
-      north_face(cur, back, jfirst == s.ny - 1 && colN, qN, g, tol, CF0, CF1, CF2, dC);
+      north_face<FLUX>(cur, back, jfirst == s.ny - 1 && colN, qN, g, tol, CF0, CF1, CF2, dC);
     }
   }
 
@@ -331,13 +331,13 @@ __device__ __forceinline__ void march_nl_dir(const Scen<real> &s, const Consts &
 
     real GN0, GN1, GN2, dN, GS0, GS1, GS2, dS;
     if (!down) {
-      north_face(cur, nxt, j == s.ny - 1 && colN, qN, g, tol, GN0, GN1, GN2, dN);
+      north_face<FLUX>(cur, nxt, j == s.ny - 1 && colN, qN, g, tol, GN0, GN1, GN2, dN);
       GS0 = CF0;
       GS1 = CF1;
       GS2 = CF2;
       dS = dC;
     } else {
-      y_face(nxt, cur, g, tol, GS0, GS1, GS2);
+      y_face<FLUX>(nxt, cur, g, tol, GS0, GS1, GS2);
       dS = dmax(real(0), -nxt.nr);
       if (j == 0 && colS) {
         inflow_flux(qS, cur.sh, g, GS0, GS2);
@@ -349,7 +349,7 @@ __device__ __forceinline__ void march_nl_dir(const Scen<real> &s, const Consts &
       dN = dC;
     }
     real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
-    east_west_faces(cur, faceW && j >= s.seg_first[0] && j <= s.seg_last[0], qW,
+    east_west_faces<FLUX>(cur, faceW && j >= s.seg_first[0] && j <= s.seg_last[0], qW,
                     faceE && j >= s.seg_first[1] && j <= s.seg_last[1], qE, g, tol, FE0, FE1, FE2,
                     FW0, FW1, FW2, dE, dW);
 
@@ -401,13 +401,13 @@ __device__ __forceinline__ void march_nl_dir(const Scen<real> &s, const Consts &
   if (STAGE == 2) publish_min(s, lane, mloc, flags);
 }
 
-template <typename real, int STAGE>
+template <typename real, int STAGE, int FLUX>
 __device__ __forceinline__ void march_nl(const Scen<real> &s, const Consts &c, int strip, int seg,
                                          int R, int lane) {
   if (seg & 1)
-    march_nl_dir<real, STAGE, true>(s, c, strip, seg, R, lane);
+    march_nl_dir<real, STAGE, FLUX, true>(s, c, strip, seg, R, lane);
   else
-    march_nl_dir<real, STAGE, false>(s, c, strip, seg, R, lane);
+    march_nl_dir<real, STAGE, FLUX, false>(s, c, strip, seg, R, lane);
 }
 
 // Work item of a wavefront.  Workgroups go to the 8 XCDs round-robin
@@ -431,11 +431,11 @@ __device__ __forceinline__ int stage_item(const Launch &L, int &item) {
   return 1;
 }
 
-template <typename real, int STAGE>
+template <typename real, int STAGE, int FLUX>
 __global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch L) {
   int item;
   if (!stage_item<STAGE>(L, item)) return;
-  march_nl<real, STAGE>(s, c, item % L.nstrips, item / L.nstrips, L.R, threadIdx.x & 63);
+  march_nl<real, STAGE, FLUX>(s, c, item % L.nstrips, item / L.nstrips, L.R, threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------------------
@@ -566,7 +566,7 @@ __device__ __forceinline__ void limited_row(const RowLL<real> &m, const RowLL<re
   row_limits(row, tol);
 }
 
-template <typename real, int STAGE>
+template <typename real, int STAGE, int FLUX>
 __device__ __forceinline__ void march_ll(const Scen<real> &s, const Consts &c, int strip, int seg,
                                          int R, int lane) {
   const double dtd = s.ctrl->dt;
@@ -612,7 +612,7 @@ __device__ __forceinline__ void march_ll(const Scen<real> &s, const Consts &c, i
     load_row_ll<real, STAGE>(s, src, j0 + 1, ci, mx, rain, gdt, tol, rc);
     limited_row(rz, ra, rb, thx, thy, tol, prev);
     limited_row(ra, rb, rc, thx, thy, tol, cur);
-    y_face(prev, cur, g, tol, GS0, GS1, GS2);
+    y_face<FLUX>(prev, cur, g, tol, GS0, GS1, GS2);
     dS = dmax(real(0), -prev.nr);
     if (j0 == 0 && colS) {
       inflow_flux(qS, cur.sh, g, GS0, GS2);
@@ -637,9 +637,9 @@ __device__ __forceinline__ void march_ll(const Scen<real> &s, const Consts &c, i
     limited_row(rb, rc, rd, thx, thy, tol, nxt);
 
     real GN0, GN1, GN2, dN;
-    north_face(cur, nxt, j == s.ny - 1 && colN, qN, g, tol, GN0, GN1, GN2, dN);
+    north_face<FLUX>(cur, nxt, j == s.ny - 1 && colN, qN, g, tol, GN0, GN1, GN2, dN);
     real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
-    east_west_faces(cur, faceW && j >= s.seg_first[0] && j <= s.seg_last[0], qW,
+    east_west_faces<FLUX>(cur, faceW && j >= s.seg_first[0] && j <= s.seg_last[0], qW,
                     faceE && j >= s.seg_first[1] && j <= s.seg_last[1], qE, g, tol, FE0, FE1, FE2,
                     FW0, FW1, FW2, dE, dW);
 
@@ -677,11 +677,11 @@ __device__ __forceinline__ void march_ll(const Scen<real> &s, const Consts &c, i
   if (STAGE == 2) publish_min(s, lane, mloc, flags);
 }
 
-template <typename real, int STAGE>
+template <typename real, int STAGE, int FLUX>
 __global__ void __launch_bounds__(256) k_stage_ll(Scen<real> s, Consts c, Launch L) {
   int item;
   if (!stage_item<STAGE>(L, item)) return;
-  march_ll<real, STAGE>(s, c, item % L.nstrips, item / L.nstrips, L.R, threadIdx.x & 63);
+  march_ll<real, STAGE, FLUX>(s, c, item % L.nstrips, item / L.nstrips, L.R, threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------------------
@@ -698,7 +698,7 @@ struct Item {
   int sid, strip, seg, pad;
 };
 
-template <typename real, int STAGE, int VARIANT>
+template <typename real, int STAGE, int VARIANT, int FLUX>
 __global__ void __launch_bounds__(256) k_batch_stage(const Scen<real> *__restrict__ scens,
                                                      const Item *__restrict__ items, int nitems,
                                                      Consts c, int R, int wpb) {
@@ -711,9 +711,9 @@ __global__ void __launch_bounds__(256) k_batch_stage(const Scen<real> *__restric
     const int seg = __builtin_amdgcn_readfirstlane(items[it].seg);
     const Scen<real> s = scens[sid];
     if (VARIANT == 1)
-      march_ll<real, STAGE>(s, c, strip, seg, R, lane);
+      march_ll<real, STAGE, FLUX>(s, c, strip, seg, R, lane);
     else
-      march_nl<real, STAGE>(s, c, strip, seg, R, lane);
+      march_nl<real, STAGE, FLUX>(s, c, strip, seg, R, lane);
   }
 }
 
@@ -919,21 +919,31 @@ Launch make_launch(int nx, int ny, int variant, int R, int wpb) {
   return L;
 }
 
+// Kernel instantiation for (stage, variant, flux).
+template <typename real, int STAGE, int FLUX>
+void queue_stage_kernel(int variant, const Scen<real> &s, const Consts &c, const Launch &L,
+                        hipStream_t st) {
+  const dim3 block(64 * L.wpb);
+  const dim3 grid((L.nitems + L.wpb - 1) / L.wpb);
+  if (variant == 1)
+    hipLaunchKernelGGL((k_stage_ll<real, STAGE, FLUX>), grid, block, 0, st, s, c, L);
+  else
+    hipLaunchKernelGGL((k_stage_nl<real, STAGE, FLUX>), grid, block, 0, st, s, c, L);
+}
+
 template <typename real>
 hipError_t launch_stage(int stage, int variant, const Scen<real> &s, const Consts &c,
                         const Launch &L, hipStream_t st) {
-  const dim3 block(64 * L.wpb);
-  const dim3 grid((L.nitems + L.wpb - 1) / L.wpb);
-  if (variant == 1) {
+  if (c.flux == kFluxRoe) {
     if (stage == 1)
-      hipLaunchKernelGGL((k_stage_ll<real, 1>), grid, block, 0, st, s, c, L);
+      queue_stage_kernel<real, 1, kFluxRoe>(variant, s, c, L, st);
     else
-      hipLaunchKernelGGL((k_stage_ll<real, 2>), grid, block, 0, st, s, c, L);
+      queue_stage_kernel<real, 2, kFluxRoe>(variant, s, c, L, st);
   } else {
     if (stage == 1)
-      hipLaunchKernelGGL((k_stage_nl<real, 1>), grid, block, 0, st, s, c, L);
+      queue_stage_kernel<real, 1, kFluxHLL>(variant, s, c, L, st);
     else
-      hipLaunchKernelGGL((k_stage_nl<real, 2>), grid, block, 0, st, s, c, L);
+      queue_stage_kernel<real, 2, kFluxHLL>(variant, s, c, L, st);
   }
   return hipGetLastError();
 }
@@ -961,22 +971,33 @@ hipError_t launch_diag(const Scen<real> &s, const Consts &c, double *partials, i
   return hipGetLastError();
 }
 
+template <typename real, int STAGE, int FLUX>
+void queue_batch_kernel(int variant, const Scen<real> *scens, const Item *it, int nitems,
+                        const Consts &c, int R, int wpb, int blocks, hipStream_t st) {
+  const dim3 block(64 * wpb), grid(blocks);
+  if (variant == 1)
+    hipLaunchKernelGGL((k_batch_stage<real, STAGE, 1, FLUX>), grid, block, 0, st, scens, it, nitems,
+                       c, R, wpb);
+  else
+    hipLaunchKernelGGL((k_batch_stage<real, STAGE, 0, FLUX>), grid, block, 0, st, scens, it, nitems,
+                       c, R, wpb);
+}
+
 template <typename real>
 hipError_t launch_batch_stage(int stage, int variant, const Scen<real> *scens, const void *items,
                               int nitems, const Consts &c, int R, int wpb, int blocks,
                               hipStream_t st) {
   const Item *it = (const Item *)items;
-  const dim3 block(64 * wpb), grid(blocks);
-  if (variant == 1) {
+  if (c.flux == kFluxRoe) {
     if (stage == 1)
-      hipLaunchKernelGGL((k_batch_stage<real, 1, 1>), grid, block, 0, st, scens, it, nitems, c, R, wpb);
+      queue_batch_kernel<real, 1, kFluxRoe>(variant, scens, it, nitems, c, R, wpb, blocks, st);
     else
-      hipLaunchKernelGGL((k_batch_stage<real, 2, 1>), grid, block, 0, st, scens, it, nitems, c, R, wpb);
+      queue_batch_kernel<real, 2, kFluxRoe>(variant, scens, it, nitems, c, R, wpb, blocks, st);
   } else {
     if (stage == 1)
-      hipLaunchKernelGGL((k_batch_stage<real, 1, 0>), grid, block, 0, st, scens, it, nitems, c, R, wpb);
+      queue_batch_kernel<real, 1, kFluxHLL>(variant, scens, it, nitems, c, R, wpb, blocks, st);
     else
-      hipLaunchKernelGGL((k_batch_stage<real, 2, 0>), grid, block, 0, st, scens, it, nitems, c, R, wpb);
+      queue_batch_kernel<real, 2, kFluxHLL>(variant, scens, it, nitems, c, R, wpb, blocks, st);
   }
   return hipGetLastError();
 }
@@ -1009,24 +1030,33 @@ hipError_t launch_batch_status(Ctrl *const *ctrls, int n, unsigned *out, hipStre
 
 // Workgroups of the persistent batched launch: the number that can be
 // resident at once for this kernel and workgroup size on the device.
+template <typename real, int STAGE, int FLUX>
+hipError_t batch_occupancy(int variant, int threads, int *per) {
+  return variant == 1
+             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_batch_stage<real, STAGE, 1, FLUX>,
+                                                            threads, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_batch_stage<real, STAGE, 0, FLUX>,
+                                                            threads, 0);
+}
+
 template <typename real>
-int batch_blocks(int stage, int variant, int wpb) {
+int batch_blocks(int stage, int variant, int flux, int wpb) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1024;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1024;
   const int threads = 64 * wpb;
   hipError_t e;
-  if (variant == 1)
-    e = stage == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_stage<real, 1, 1>, threads, 0)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_stage<real, 2, 1>, threads, 0);
+  if (flux == kFluxRoe)
+    e = stage == 1 ? batch_occupancy<real, 1, kFluxRoe>(variant, threads, &per)
+                   : batch_occupancy<real, 2, kFluxRoe>(variant, threads, &per);
   else
-    e = stage == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_stage<real, 1, 0>, threads, 0)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_stage<real, 2, 0>, threads, 0);
+    e = stage == 1 ? batch_occupancy<real, 1, kFluxHLL>(variant, threads, &per)
+                   : batch_occupancy<real, 2, kFluxHLL>(variant, threads, &per);
   if (e != hipSuccess || per < 1) per = 1;
   return per * cus;
 }
-template int batch_blocks<double>(int, int, int);
-template int batch_blocks<float>(int, int, int);
+template int batch_blocks<double>(int, int, int, int);
+template int batch_blocks<float>(int, int, int, int);
 
 hipError_t launch_plan_batch(Ctrl *const *ctrls, const PlanArgs *pa, int n, int mode, double t_end,
                              int set_tend, hipStream_t st) {

@@ -26,6 +26,7 @@ FP64, FP32 = 0, 1
 NL, LL = 0, 1
 WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
 BC_WALL, BC_INFLOW_Q = 0, 1
+FLUX_HLL, FLUX_ROE = 0, 1
 
 _STATUS = {0: "DG2_OK", -1: "DG2_EINVAL", -2: "DG2_ENOMEM", -3: "DG2_EHIP", -4: "DG2_ESTATE",
            -5: "DG2_ENUMERIC", -6: "DG2_EUNSUPPORTED"}
@@ -42,7 +43,8 @@ class Config(ctypes.Structure):
     _fields_ = [("nx", c_int32), ("ny", c_int32), ("dx", c_double), ("dy", c_double),
                 ("x0", c_double), ("y0", c_double), ("prec", c_int32), ("variant", c_int32),
                 ("g", c_double), ("cfl", c_double), ("tol_dry", c_double),
-                ("ll_threshold", c_double), ("dt_max", c_double), ("hip_stream", c_void_p)]
+                ("ll_threshold", c_double), ("dt_max", c_double), ("hip_stream", c_void_p),
+                ("flux", c_int32)]
 
 
 # name -> (restype, argtypes)
@@ -134,13 +136,15 @@ class Sim:
     def __init__(self, nx: int, ny: int, dx: float, dy: Optional[float] = None, *,
                  precision: str = "fp64", variant: str = "NL", g: float = 9.81,
                  cfl: float = 0.3, tol_dry: float = 1e-5, ll_threshold: float = 10.0,
-                 dt_max: float = 1.0, x0: float = 0.0, y0: float = 0.0, stream=None):
+                 dt_max: float = 1.0, x0: float = 0.0, y0: float = 0.0, stream=None,
+                 flux: str = "HLL"):
         self._lib = load_library()
         self._ctx = c_void_p()
         cfg = Config()
         self._lib.dg2_config_default(byref(cfg), nx, ny, dx, dx if dy is None else dy)
         cfg.prec = {"fp64": FP64, "fp32": FP32}[precision]
         cfg.variant = {"NL": NL, "LL": LL}[variant]
+        cfg.flux = {"HLL": FLUX_HLL, "ROE": FLUX_ROE}[flux]
         cfg.g, cfg.cfl, cfg.tol_dry, cfg.ll_threshold, cfg.dt_max = g, cfl, tol_dry, ll_threshold, dt_max
         cfg.x0, cfg.y0 = x0, y0
         if stream == "torch":
@@ -415,7 +419,8 @@ def sim_from_scenario(sc, stream=None, precision: Optional[str] = None,
     """A ``Sim`` loaded with a ``workloads.Scenario`` (argument marshalling only)."""
     s = Sim(sc.nx, sc.ny, sc.dx, sc.dy, precision=precision or sc.precision,
             variant=variant or sc.variant, g=sc.g, cfl=sc.cfl, tol_dry=sc.tol_dry,
-            ll_threshold=sc.theta, dt_max=sc.dt_max, x0=sc.x0, y0=sc.y0, stream=stream)
+            ll_threshold=sc.theta, dt_max=sc.dt_max, x0=sc.x0, y0=sc.y0, stream=stream,
+            flux=sc.flux)
     s.set_dem_corners(sc.Z)
     s.set_manning(sc.manning)
     for b in sc.inflows:

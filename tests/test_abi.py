@@ -38,10 +38,28 @@ def test_binding_covers_the_header():
     assert sorted(dg2.exported_symbols()) == _declared()
 
 
-def test_config_struct_matches_header_layout():
-    # int32 nx, ny | 4 doubles | int32 prec, variant | 5 doubles | pointer
-    assert ctypes.sizeof(dg2.Config) == 8 + 32 + 8 + 40 + 8
-    assert dg2.Config.hip_stream.offset == 88
+def test_config_struct_matches_header_layout(tmp_path):
+    """The ctypes mirror of dg2_config against the C compiler's layout of the
+    header's struct (size and every field offset)."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        pytest.skip("no C compiler")
+    fields = [f[0] for f in dg2.Config._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"dg2.h\"\nint main(void) {\n"
+                   '  printf("%zu\\n", sizeof(dg2_config));\n'
+                   + "".join('  printf("%%zu\\n", offsetof(dg2_config, %s));\n' % f for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(dg2.Config)
+    assert out[1:] == [getattr(dg2.Config, f).offset for f in fields]
 
 
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):
