@@ -285,6 +285,49 @@ def adjoint_case(n: int = 512, dx: float = 2.0, seed: int = 5, steps: int = 2000
                 model_scale=0.8, gauges=gauges, checkpoint_every=100)
 
 
+def thacker_bowl(dx: float = 40.0, L: float = 4000.0, h0: float = 1.0, r0: float = 2000.0,
+                 g: float = 9.81, tau: float = 1756.2, precision: str = "fp64",
+                 variant: str = "NL") -> Scenario:
+    """Curved oscillatory flow in a frictionless parabolic bowl (Thacker's
+    solution; the long-run test of Sec. 2.3, period tau = 1756.2 s).
+
+    Domain [-L, L]^2 (8 km square), cells of dx (40 m: 200 x 200).  Bed
+    z = -h0 (1 - r^2/a^2) with a chosen so that the period 2 pi a /
+    sqrt(8 g h0) equals tau (a = 2476.7 m for h0 = 1 m, g = 9.81); r0 = 2000 m
+    sets the amplitude A = (a^4 - r0^4)/(a^4 + r0^4).  At t = 0 the water is
+    at rest with the concave surface of the exact solution (maximally dry).
+    Walls far outside the wet region, no friction.  The exact solution is in
+    ``thacker_exact``.
+    """
+    a = tau * np.sqrt(8.0 * g * h0) / (2.0 * np.pi)
+    n = int(round(2.0 * L / dx))
+    X, Y = corner_xy(n, n, dx, dx, -L, -L)
+    Z = -h0 * (1.0 - (X * X + Y * Y) / (a * a))
+    h, _, _ = thacker_exact(X, Y, 0.0, h0=h0, a=a, r0=r0, g=g)
+    return Scenario(name="thacker_%dx%d" % (n, n), nx=n, ny=n, dx=dx, dy=dx, Z=Z, surface=h,
+                    is_eta=False, manning=0.0, cfl=0.3, dt_max=1e6, g=g, variant=variant,
+                    precision=precision, x0=-L, y0=-L)
+
+
+def thacker_exact(x, y, t, h0: float = 1.0, a: float = None, r0: float = 2000.0,
+                  g: float = 9.81, tau: float = 1756.2):
+    """Thacker's curved oscillatory solution at time t: depth h >= 0 and the
+    velocities (u, v), with a from tau when not given (as in thacker_bowl)."""
+    if a is None:
+        a = tau * np.sqrt(8.0 * g * h0) / (2.0 * np.pi)
+    w = np.sqrt(8.0 * g * h0) / a
+    A = (a ** 4 - r0 ** 4) / (a ** 4 + r0 ** 4)
+    c, sn = np.cos(w * t), np.sin(w * t)
+    r2 = (x * x + y * y) / (a * a)
+    eta = h0 * (np.sqrt(1.0 - A * A) / (1.0 - A * c) - 1.0
+                - r2 * ((1.0 - A * A) / (1.0 - A * c) ** 2 - 1.0))
+    z = -h0 * (1.0 - r2)
+    h = np.maximum(eta - z, 0.0)
+    f = 0.5 * w * A * sn / (1.0 - A * c)
+    wet = h > 0.0
+    return h, np.where(wet, f * x, 0.0), np.where(wet, f * y, 0.0)
+
+
 def random_modes(nx: int, ny: int, seed: int, wet_fraction: float = 0.8,
                  depth: float = 1.0, slope: float = 0.3, speed: float = 1.0) -> Tuple[np.ndarray, np.ndarray]:
     """Random 9-plane mode state and 3-plane bed modes for single-stage checks.

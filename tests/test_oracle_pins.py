@@ -547,3 +547,27 @@ def test_paper_constants_fixture():
     assert prm.tol == c["tol_dry"]["value"]
     assert prm.theta == c["shock_detector_threshold"]["value"]
     assert abs(1.0 / O.SQRT3 - c["gauss_point_offset"]["value"]) < 1e-16
+
+
+# ---------------------------------------------------------------------------
+# Exact solution with wetting and drying: Thacker's curved oscillation in a
+# parabolic bowl (the long-run test of Sec. 2.3)
+# ---------------------------------------------------------------------------
+
+def test_thacker_bowl_converges_to_the_exact_solution():
+    """Half a period (t = tau/2, maximally wet) on 160 m and 80 m cells: the
+    depth converges to Thacker's solution at about second order over the
+    whole bowl, fronts included, and mass is exact."""
+    tau = 1756.2
+    errs = []
+    for dx in (160.0, 80.0):
+        sc = WL.thacker_bowl(dx=dx)
+        U, bed, prm = O.setup(sc)
+        r = O.run(U, bed, prm, t_end=tau / 2)
+        assert r.t == tau / 2
+        XC, YC = WL.cell_xy(sc.nx, sc.ny, dx, dx, sc.x0, sc.y0)
+        he, ue, _ = WL.thacker_exact(XC, YC, tau / 2)
+        errs.append(float(np.abs(r.U[0, 0].numpy() - he).mean()))
+        assert abs(O.mass(r.U, prm) - O.mass(U, prm)) <= 1e-13 * O.mass(U, prm)
+    assert errs[1] < 6e-4
+    assert errs[0] / errs[1] > 2.8  # observed order above 1.5
