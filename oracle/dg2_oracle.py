@@ -45,6 +45,9 @@ library implements):
     depth at the centre and the four Gauss points, once per time step with
     the full dt, increments added to the discharge modes;
   * walls: mirror ghost cells; discharge inflow: prescribed face flux;
+    water-level boundary: a ghost at the prescribed level whose normal
+    velocity keeps the outgoing Riemann invariant, inflow capped at critical
+    speed; open boundary: a ghost holding the inside cell's mean state;
     rainfall: added to the mean depth mode before friction;
   * cells whose mean depth is at or below the drying tolerance get zero
     discharge modes after each stage; depths are never clipped.
@@ -156,6 +159,25 @@ class InflowBC:
 
 
 @dataclass
+class LevelBC:
+    """Water-level boundary: the free-surface elevation eta(t) (piecewise
+    linear in the samples, held outside) along a boundary segment."""
+    side: int
+    first: int
+    last: int
+    t: torch.Tensor
+    eta: torch.Tensor
+
+
+@dataclass
+class OpenBC:
+    """Open (transmissive) boundary segment."""
+    side: int
+    first: int
+    last: int
+
+
+@dataclass
 class Params:
     nx: int
     ny: int
@@ -170,22 +192,29 @@ class Params:
     flux: str = "HLL"  # face flux: "HLL" (default reading) or "ROE" (the paper's choice)
     manning: object = 0.0  # float or (ny, nx) tensor
     inflows: List[InflowBC] = field(default_factory=list)
+    levels: List[LevelBC] = field(default_factory=list)
+    opens: List[OpenBC] = field(default_factory=list)
     rain: Optional[Tuple[float, float, float]] = None
     fixed_dt: float = 0.0
     x0: float = 0.0
     y0: float = 0.0
 
 
-def hydrograph_value(bc: InflowBC, t: float) -> torch.Tensor:
-    """Piecewise-linear interpolation of the hydrograph, held constant outside."""
-    ts = bc.t.to(F64)
+def _table_value(ts, vs, t: float):
+    """Piecewise-linear interpolation of a time table, held constant outside."""
+    ts = ts.to(F64)
     if t <= float(ts[0]):
-        return bc.Q[0]
+        return vs[0]
     if t >= float(ts[-1]):
-        return bc.Q[-1]
+        return vs[-1]
     k = int(torch.searchsorted(ts, torch.tensor([t], dtype=F64), right=True)[0]) - 1
     w = (t - float(ts[k])) / (float(ts[k + 1]) - float(ts[k]))
-    return bc.Q[k] * (1.0 - w) + bc.Q[k + 1] * w
+    return vs[k] * (1.0 - w) + vs[k + 1] * w
+
+
+def hydrograph_value(bc: InflowBC, t: float) -> torch.Tensor:
+    """Discharge of an inflow hydrograph at time t."""
+    return _table_value(bc.t, bc.Q, t)
 
 
 # ---------------------------------------------------------------------------
@@ -384,6 +413,69 @@ def spatial_operator(W: torch.Tensor, bed: Bed, prm: Params, t_stage: float) -> 
         else:
             f = inflow_face_flux(q_in, hsn[ny, a:b], g)
             Fy[:, ny, a:b] = torch.stack([-f[0], f[2], f[1]])
+
+    # ---- water-level and open boundary faces ------------------------------
+    # The outside of the face is a ghost state and the face flux is the
+    # two-argument flux between inside and ghost, oriented along +x / +y.
+    # Open boundary: the inside cell's mean state (zero gradient of the cell
+    # average; copying the face limit itself leaves the slope equations of
+    # the boundary cell without any upwinding, and an outgoing shock then
+    # grows unstable).
+    # Level boundary: depth h_b = max(0, eta(t) - z_face); normal velocity
+    # from the Riemann invariant that leaves the domain (u - 2c at a west or
+    # south face, u + 2c at an east or north face), so that a subcritical
+    # boundary carries exactly the prescribed level; an inflow is capped at
+    # critical speed c_b (a dry or supercritical inside sends no invariant
+    # back); tangential velocity from the inside.
+    def ghost_face(side, a, b, eta):
+        if side in (WEST, EAST):
+            col = 0 if side == WEST else nx
+            if side == WEST:
+                h_in, u_in, v_in = hsp[a:b, col], up[a:b, col], vp[a:b, col]
+            else:
+                h_in, u_in, v_in = hsm[a:b, col], um[a:b, col], vm[a:b, col]
+            zf = bed.zfx[a:b, col]
+        else:
+            row = 0 if side == SOUTH else ny
+            if side == SOUTH:  # y-face states in (h, normal v, tangential u)
+                h_in, u_in, v_in = hss[row, a:b], vs[row, a:b], us[row, a:b]
+            else:
+                h_in, u_in, v_in = hsn[row, a:b], vn[row, a:b], un_[row, a:b]
+            zf = bed.zfy[row, a:b]
+        if eta is None:
+            # the inside cell's mean state, through the dummy limit
+            if side in (WEST, EAST):
+                cc = 0 if side == WEST else nx - 1
+                hm0, qn0, qt0 = W[H, M0][a:b, cc], W[QX, M0][a:b, cc], W[QY, M0][a:b, cc]
+            else:
+                rr = 0 if side == SOUTH else ny - 1
+                hm0, qn0, qt0 = W[H, M0][rr, a:b], W[QY, M0][rr, a:b], W[QX, M0][rr, a:b]
+            hg, ug, vg = dummy_limits(hm0, qn0, qt0, tol)
+        else:
+            hg = torch.clamp(eta - zf, min=0.0)
+            cg, cin = torch.sqrt(g * hg), torch.sqrt(g * h_in)
+            if side in (WEST, SOUTH):
+                ug = torch.minimum(u_in - 2.0 * cin + 2.0 * cg, cg)
+            else:
+                ug = torch.maximum(u_in + 2.0 * cin - 2.0 * cg, -cg)
+            vg = v_in
+        if side in (WEST, SOUTH):
+            f = face_flux(prm, hg, ug, vg, h_in, u_in, v_in)
+        else:
+            f = face_flux(prm, h_in, u_in, v_in, hg, ug, vg)
+        if side == WEST:
+            Fx[:, a:b, 0] = f
+        elif side == EAST:
+            Fx[:, a:b, nx] = f
+        elif side == SOUTH:
+            Fy[:, 0, a:b] = torch.stack([f[0], f[2], f[1]])
+        else:
+            Fy[:, ny, a:b] = torch.stack([f[0], f[2], f[1]])
+
+    for bc in prm.levels:
+        ghost_face(bc.side, bc.first, bc.last + 1, _table_value(bc.t, bc.eta, t_stage).to(F64))
+    for bc in prm.opens:
+        ghost_face(bc.side, bc.first, bc.last + 1, None)
 
     # ---- per element: dummy modes (Eq. 5) and operators (Eq. 4) ------------
     FE, FW = Fx[:, :, 1:], Fx[:, :, :-1]

@@ -19,6 +19,8 @@ import torch
 from oracle import dg2_oracle as O
 from paper_2010_02003_amd import workloads as WL
 
+from exact_riemann import exact_riemann
+
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 G = 9.81
 TOL = 1e-5
@@ -102,62 +104,6 @@ def test_roe_lake_at_rest_and_high_wall_stay_still():
     prm = O.Params(nx=nx, ny=ny, dx=1.0, dy=1.0, manning=0.02, flux="ROE")
     r = O.run(U, O.bed_from_corners(Z), prm, steps=200)
     assert float(r.U[1:].abs().max()) < 1e-13
-
-
-# ---------------------------------------------------------------------------
-# Exact Riemann solver for the 1D shallow water equations over a flat bed
-# (two waves, each a shock or a rarefaction; wet states on both sides)
-# ---------------------------------------------------------------------------
-
-def _wave_function(h, hK):
-    """Velocity change across a wave from depth hK to depth h, and its derivative."""
-    cK = math.sqrt(G * hK)
-    if h <= hK:  # rarefaction
-        c = math.sqrt(G * h)
-        return 2.0 * (c - cK), G / c
-    gk = math.sqrt(0.5 * G * (h + hK) / (h * hK))  # shock
-    return (h - hK) * gk, gk - G * (h - hK) / (4.0 * gk * h * h)
-
-
-def exact_riemann(hL, uL, hR, uR, xi):
-    """Depth and velocity of the exact solution at x/t = xi."""
-    h = 0.5 * (hL + hR)
-    for _ in range(100):
-        fL, dL = _wave_function(h, hL)
-        fR, dR = _wave_function(h, hR)
-        step = (fL + fR + uR - uL) / (dL + dR)
-        h = max(h - step, 1e-12)
-        if abs(step) < 1e-15 * h:
-            break
-    fL, _ = _wave_function(h, hL)
-    fR, _ = _wave_function(h, hR)
-    hs, us = h, 0.5 * (uL + uR) + 0.5 * (fR - fL)
-    cL, cR, cs = math.sqrt(G * hL), math.sqrt(G * hR), math.sqrt(G * hs)
-    out_h, out_u = np.empty_like(xi), np.empty_like(xi)
-    for k, x in enumerate(xi):
-        if x <= us:  # left of the contact: left wave
-            if hs > hL:  # shock
-                sL = uL - cL * math.sqrt(0.5 * hs * (hs + hL)) / hL
-                out_h[k], out_u[k] = (hL, uL) if x < sL else (hs, us)
-            elif x < uL - cL:
-                out_h[k], out_u[k] = hL, uL
-            elif x > us - cs:
-                out_h[k], out_u[k] = hs, us
-            else:
-                c = (uL + 2.0 * cL - x) / 3.0
-                out_h[k], out_u[k] = c * c / G, x + c
-        else:
-            if hs > hR:
-                sR = uR + cR * math.sqrt(0.5 * hs * (hs + hR)) / hR
-                out_h[k], out_u[k] = (hR, uR) if x > sR else (hs, us)
-            elif x > uR + cR:
-                out_h[k], out_u[k] = hR, uR
-            elif x < us + cs:
-                out_h[k], out_u[k] = hs, us
-            else:
-                c = (x - uR + 2.0 * cR) / 3.0
-                out_h[k], out_u[k] = c * c / G, x - c
-    return out_h, out_u, hs, us
 
 
 def test_exact_riemann_solver_reproduces_stoker_golden():
