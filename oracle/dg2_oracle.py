@@ -456,9 +456,13 @@ def spatial_operator(W: torch.Tensor, bed: Bed, prm: Params, t_stage: float) -> 
             cg, cin = torch.sqrt(g * hg), torch.sqrt(g * h_in)
             if side in (WEST, SOUTH):
                 ug = torch.minimum(u_in - 2.0 * cin + 2.0 * cg, cg)
+                entering = ug > 0.0
             else:
                 ug = torch.maximum(u_in + 2.0 * cin - 2.0 * cg, -cg)
-            vg = v_in
+                entering = ug < 0.0
+            # water entering from the reservoir brings no tangential motion;
+            # water leaving keeps its own
+            vg = torch.where(entering, torch.zeros_like(v_in), v_in)
         if side in (WEST, SOUTH):
             f = face_flux(prm, hg, ug, vg, h_in, u_in, v_in)
         else:
@@ -789,10 +793,12 @@ def params_from_scenario(sc) -> Params:
     man = sc.manning
     man = _t(man) if isinstance(man, np.ndarray) else float(man)
     infl = [InflowBC(b.side, b.first, b.last, _t(b.t), _t(b.Q)) for b in sc.inflows]
+    levs = [LevelBC(b.side, b.first, b.last, _t(b.t), _t(b.eta)) for b in sc.levels]
+    opens = [OpenBC(side, first, last) for side, first, last in sc.opens]
     return Params(nx=sc.nx, ny=sc.ny, dx=sc.dx, dy=sc.dy, g=sc.g, tol=sc.tol_dry, cfl=sc.cfl,
                   dt_max=sc.dt_max, theta=sc.theta, variant=sc.variant, manning=man,
-                  inflows=infl, rain=sc.rain, fixed_dt=sc.fixed_dt, x0=sc.x0, y0=sc.y0,
-                  flux=sc.flux)
+                  inflows=infl, levels=levs, opens=opens, rain=sc.rain, fixed_dt=sc.fixed_dt,
+                  x0=sc.x0, y0=sc.y0, flux=sc.flux)
 
 
 def setup(sc):

@@ -45,6 +45,17 @@ class Inflow:
 
 
 @dataclass
+class Level:
+    """Water-level hydrograph imposed along one boundary segment."""
+
+    side: int
+    first: int
+    last: int
+    t: np.ndarray  # sample times (s), increasing
+    eta: np.ndarray  # free-surface elevation (m)
+
+
+@dataclass
 class Scenario:
     """Everything that defines one run: grid, inputs and run controls."""
 
@@ -71,6 +82,8 @@ class Scenario:
     t_end: Optional[float] = None
     fixed_dt: float = 0.0
     inflows: List[Inflow] = field(default_factory=list)
+    levels: List[Level] = field(default_factory=list)
+    opens: List[Tuple[int, int, int]] = field(default_factory=list)  # (side, first, last)
     rain: Optional[Tuple[float, float, float]] = None  # (rate m/s, t_begin, t_end)
     gauges: Optional[np.ndarray] = None  # (ng, 2) x, y in m
     x0: float = 0.0

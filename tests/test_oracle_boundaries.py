@@ -13,7 +13,13 @@ boundary in Sec. 3.1.1), against exact solutions.
   relation), so the level just inside is the prescribed one to 3e-4 m;
 * open boundaries let Stoker's dam-break waves leave a truncated domain: the
   depth converges to the exact infinite-domain solution;
-* a uniform flow passes through open boundaries unchanged.
+* a uniform flow passes through open boundaries unchanged;
+* water entering through a level boundary brings no tangential motion: in a
+  lake drifting along the boundary, the tangential discharge converges to
+  the exact solution, where the tangential velocity is a passive tracer,
+  zero behind the contact;
+* water leaving through a level boundary keeps its tangential velocity: an
+  oblique stream at the prescribed level leaves unchanged.
 """
 import math
 
@@ -130,5 +136,56 @@ def test_uniform_flow_passes_through_open_boundaries():
     U = O.initial_state(Z, np.full_like(Z, h), False, qx=np.full_like(Z, h * u), qy=np.full_like(Z, h * v))
     opens = [O.OpenBC(s, 0, (ny if s in (O.WEST, O.EAST) else nx) - 1) for s in range(4)]
     prm = O.Params(nx=nx, ny=ny, dx=1.0, dy=1.0, opens=opens)
+    r = O.run(U, O.bed_from_corners(Z), prm, steps=50)
+    assert float((r.U - U).abs().max()) < 1e-13
+
+
+def _bore_with_current_l1(nx, T=20.0, L=100.0, h0=1.0, hb=1.5, v0=0.5):
+    """A bore from a level rise entering a lake that drifts along the
+    boundary at v0 (y-uniform, open north and south): water entering from
+    the reservoir brings no tangential motion, so v is a passive tracer that
+    is 0 behind the contact at the middle-state speed u* and v0 ahead of it."""
+    dx = L / nx
+    X, _ = WL.corner_xy(nx, 2, dx, dx)
+    Z = np.zeros_like(X)
+    U = O.initial_state(Z, np.full_like(Z, h0), False, qy=np.full_like(Z, h0 * v0))
+    lev = [O.LevelBC(O.WEST, 0, 1, torch.tensor([0.0], dtype=F64), torch.tensor([hb], dtype=F64))]
+    opens = [O.OpenBC(O.SOUTH, 0, nx - 1), O.OpenBC(O.NORTH, 0, nx - 1)]
+    prm = O.Params(nx=nx, ny=2, dx=dx, dy=dx, cfl=0.3, levels=lev, opens=opens)
+    r = O.run(U, O.bed_from_corners(Z), prm, t_end=T)
+    ub = 2.0 * (math.sqrt(G * hb) - math.sqrt(G * h0))
+    sub = 32
+    xf = (np.arange(nx * sub) + 0.5) * dx / sub
+    he, _, _, us = exact_riemann(hb, ub, h0, 0.0, xf / T)
+    qy = np.where(xf / T < us, 0.0, he * v0).reshape(nx, sub).mean(axis=1)
+    got = r.U[2, 0].numpy()
+    assert np.allclose(got[0], got[1], rtol=0, atol=1e-13)  # stays y-uniform
+    return np.abs(got[0] - qy).mean(), us
+
+
+def test_level_boundary_inflow_brings_no_tangential_motion():
+    e1, us = _bore_with_current_l1(100)
+    e2, _ = _bore_with_current_l1(200)
+    # the contact has moved u* T = 28 m into the domain: water behind it is
+    # at rest along y; a ghost carrying the lake's v0 would leave qy ~ h v0
+    # (0.75) there, an L1 error near 0.2.  HLL smears the contact, so the
+    # error falls at about half order.
+    assert us * 20.0 > 20.0
+    assert e1 < 1e-2
+    assert e2 < 0.85 * e1
+
+
+def test_oblique_flow_leaves_through_a_level_boundary_unchanged():
+    """Water leaving through a level boundary keeps its own tangential
+    velocity: a uniform subcritical oblique stream at the prescribed level
+    leaves through it with no change."""
+    nx, ny = 12, 5
+    X, _ = WL.corner_xy(nx, ny, 1.0, 1.0)
+    Z = np.zeros_like(X)
+    h, u, v = 0.8, -0.6, 0.4
+    U = O.initial_state(Z, np.full_like(Z, h), False, qx=np.full_like(Z, h * u), qy=np.full_like(Z, h * v))
+    lev = [O.LevelBC(O.WEST, 0, ny - 1, torch.tensor([0.0], dtype=F64), torch.tensor([h], dtype=F64))]
+    opens = [O.OpenBC(O.EAST, 0, ny - 1), O.OpenBC(O.SOUTH, 0, nx - 1), O.OpenBC(O.NORTH, 0, nx - 1)]
+    prm = O.Params(nx=nx, ny=ny, dx=1.0, dy=1.0, levels=lev, opens=opens)
     r = O.run(U, O.bed_from_corners(Z), prm, steps=50)
     assert float((r.U - U).abs().max()) < 1e-13
