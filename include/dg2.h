@@ -69,7 +69,16 @@ typedef enum { DG2_NL = 0, DG2_LL = 1 } dg2_variant;
 typedef enum { DG2_WEST = 0, DG2_EAST = 1, DG2_SOUTH = 2, DG2_NORTH = 3 } dg2_side;
 /* Boundary segments default to solid walls (mirror ghost cells).  An inflow
  * segment takes a discharge hydrograph (dg2_set_inflow_hydrograph). */
-typedef enum { DG2_BC_WALL = 0, DG2_BC_INFLOW_Q = 1 } dg2_bc;
+/* Boundary kinds of a segment of one side (the rest of the side is a wall).
+ * DG2_BC_INFLOW_Q: prescribed discharge hydrograph (dg2_set_inflow_hydrograph).
+ * DG2_BC_LEVEL: prescribed water-level hydrograph (dg2_set_level_hydrograph),
+ *   as at the west boundary of the Sec. 3.1.1 benchmark: the outside of each
+ *   face is a ghost at depth max(0, eta(t) - z_face) whose normal velocity
+ *   keeps the Riemann invariant leaving the domain (an inflow capped at the
+ *   critical speed); its tangential velocity is zero where that normal
+ *   velocity enters the domain and the inside one where it leaves.
+ * DG2_BC_OPEN: transmissive: the ghost holds the inside cell's mean state. */
+typedef enum { DG2_BC_WALL = 0, DG2_BC_INFLOW_Q = 1, DG2_BC_LEVEL = 2, DG2_BC_OPEN = 3 } dg2_bc;
 /* Two-argument face flux of Sec. 2.1.2.  DG2_FLUX_HLL (default): HLL with
  * two-rarefaction wave-speed estimates and dry-bed front speeds.
  * DG2_FLUX_ROE: Roe's solver, the paper's choice (Roe averages, no entropy
@@ -147,6 +156,12 @@ dg2_status dg2_set_boundary(dg2_ctx *ctx, int32_t side, int32_t bc, int32_t firs
  * outside.  Each RK stage uses Q at its own stage time. */
 dg2_status dg2_set_inflow_hydrograph(dg2_ctx *ctx, int32_t side, const double *t, const double *Q,
                                      int32_t n);
+
+/* Water-level hydrograph of a DG2_BC_LEVEL segment: free-surface elevation
+ * eta (m, finite) at n >= 1 increasing times t; linear in between, held
+ * outside.  Each RK stage uses eta at its own stage time. */
+dg2_status dg2_set_level_hydrograph(dg2_ctx *ctx, int32_t side, const double *t, const double *eta,
+                                    int32_t n);
 
 /* Uniform rainfall of rate (m/s, >= 0) during [t_begin, t_end]: the mean
  * depth of every element gains rate * |[t, t+dt] intersect [t_begin, t_end]|

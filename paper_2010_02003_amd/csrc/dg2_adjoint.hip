@@ -255,7 +255,7 @@ AdjGeom geom(const dg2_adj *a) {
   G.g = c->cfg.g;
   G.tol = c->cfg.tol_dry;
   for (int k = 0; k < 4; ++k) {
-    const bool on = c->inflow[k] && c->nhyd[k] > 0;
+    const bool on = side_table_on(c, k);
     G.seg_first[k] = on ? c->seg_first[k] : 1;
     G.seg_last[k] = on ? c->seg_last[k] : 0;
   }
@@ -363,8 +363,11 @@ dg2_status dg2_adj_create(dg2_ctx *c, int32_t steps, int32_t every, int32_t side
   if (c->ng < 1) return afail(nullptr, DG2_ESTATE, "the adjoint needs at least one gauge");
   if (steps < 1 || every < 1) return afail(nullptr, DG2_EINVAL, "steps and checkpoint interval must be >= 1");
   if (side < -1 || side > 3) return afail(nullptr, DG2_EINVAL, "bad control side");
-  if (side >= 0 && !(c->inflow[side] && c->nhyd[side] > 0))
+  if (side >= 0 && !(c->bkind[side] == DG2_BC_INFLOW_Q && side_table_on(c, side)))
     return afail(nullptr, DG2_ESTATE, "the control side has no inflow hydrograph");
+  for (int k = 0; k < 4; ++k)
+    if (side_active(c, k) && c->bkind[k] != DG2_BC_INFLOW_Q)
+      return afail(nullptr, DG2_EUNSUPPORTED, "the adjoint step handles walls and discharge inflows only");
 
   dg2_adj *a = new (std::nothrow) dg2_adj();
   if (!a) return afail(nullptr, DG2_ENOMEM, "host allocation failed");

@@ -369,10 +369,10 @@ dg2_status dg2_set_boundary(dg2_ctx *c, int32_t side, int32_t bc, int32_t first,
   if (side < 0 || side > 3) return fail(c, DG2_EINVAL, "bad side");
   const int len = (side == DG2_WEST || side == DG2_EAST) ? c->cfg.ny : c->cfg.nx;
   if (bc == DG2_BC_WALL) {
-    c->inflow[side] = false;
-  } else if (bc == DG2_BC_INFLOW_Q) {
+    c->bkind[side] = DG2_BC_WALL;
+  } else if (bc == DG2_BC_INFLOW_Q || bc == DG2_BC_LEVEL || bc == DG2_BC_OPEN) {
     if (first < 0 || last >= len || first > last) return fail(c, DG2_EINVAL, "bad segment");
-    c->inflow[side] = true;
+    c->bkind[side] = bc;
     c->seg_first[side] = first;
     c->seg_last[side] = last;
   } else {
@@ -382,14 +382,17 @@ dg2_status dg2_set_boundary(dg2_ctx *c, int32_t side, int32_t bc, int32_t first,
   return DG2_OK;
 }
 
-dg2_status dg2_set_inflow_hydrograph(dg2_ctx *c, int32_t side, const double *t, const double *Q,
-                                     int32_t n) {
-  if (!c) return DG2_EINVAL;
+namespace {
+
+// Store a side's time table (discharge or water level) on the device.
+dg2_status set_side_table(dg2_ctx *c, int32_t side, const double *t, const double *v, int32_t n,
+                          int kind) {
   if (side < 0 || side > 3) return fail(c, DG2_EINVAL, "bad side");
-  if (!t || !Q || n < 1) return fail(c, DG2_EINVAL, "need n >= 1 samples");
+  if (!t || !v || n < 1) return fail(c, DG2_EINVAL, "need n >= 1 samples");
   for (int k = 0; k < n; ++k) {
-    if (!std::isfinite(t[k]) || !std::isfinite(Q[k]) || Q[k] < 0)
-      return fail(c, DG2_EINVAL, "hydrograph values must be finite and Q >= 0");
+    if (!std::isfinite(t[k]) || !std::isfinite(v[k]))
+      return fail(c, DG2_EINVAL, "hydrograph values must be finite");
+    if (kind == DG2_BC_INFLOW_Q && v[k] < 0) return fail(c, DG2_EINVAL, "discharges must be >= 0");
     if (k > 0 && !(t[k] > t[k - 1])) return fail(c, DG2_EINVAL, "hydrograph times must increase");
   }
   HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
@@ -400,10 +403,25 @@ dg2_status dg2_set_inflow_hydrograph(dg2_ctx *c, int32_t side, const double *t, 
   HIPCHK(c, hipMalloc((void **)&c->hyd_t[side], n * 8), "hydrograph");
   HIPCHK(c, hipMalloc((void **)&c->hyd_Q[side], n * 8), "hydrograph");
   HIPCHK(c, hipMemcpy(c->hyd_t[side], t, n * 8, hipMemcpyHostToDevice), "hydrograph");
-  HIPCHK(c, hipMemcpy(c->hyd_Q[side], Q, n * 8, hipMemcpyHostToDevice), "hydrograph");
+  HIPCHK(c, hipMemcpy(c->hyd_Q[side], v, n * 8, hipMemcpyHostToDevice), "hydrograph");
   c->nhyd[side] = n;
+  c->hyd_kind[side] = kind;
   HIPCHK(c, queue_plan(c, kPlanOnly), "plan");
   return DG2_OK;
+}
+
+}  // namespace
+
+dg2_status dg2_set_inflow_hydrograph(dg2_ctx *c, int32_t side, const double *t, const double *Q,
+                                     int32_t n) {
+  if (!c) return DG2_EINVAL;
+  return set_side_table(c, side, t, Q, n, DG2_BC_INFLOW_Q);
+}
+
+dg2_status dg2_set_level_hydrograph(dg2_ctx *c, int32_t side, const double *t, const double *eta,
+                                    int32_t n) {
+  if (!c) return DG2_EINVAL;
+  return set_side_table(c, side, t, eta, n, DG2_BC_LEVEL);
 }
 
 dg2_status dg2_set_rainfall(dg2_ctx *c, double rate, double tb, double te) {

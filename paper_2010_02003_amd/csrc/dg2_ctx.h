@@ -30,7 +30,8 @@ struct dg2_ctx {
   std::vector<double> z0, z1x, z1y;
   // boundaries and hydrographs
   int seg_first[4] = {1, 1, 1, 1}, seg_last[4] = {0, 0, 0, 0};
-  bool inflow[4] = {false, false, false, false};
+  int bkind[4] = {0, 0, 0, 0};     // dg2_bc of each side's segment
+  int hyd_kind[4] = {0, 0, 0, 0};  // what the side's table holds: DG2_BC_INFLOW_Q or DG2_BC_LEVEL
   double *hyd_t[4] = {nullptr, nullptr, nullptr, nullptr};
   double *hyd_Q[4] = {nullptr, nullptr, nullptr, nullptr};
   int nhyd[4] = {0, 0, 0, 0};
@@ -51,6 +52,14 @@ struct dg2_ctx {
 
 namespace dg2 {
 
+// A side's hydrograph table drives its segment (inflow or level).
+inline bool side_table_on(const dg2_ctx *c, int s) {
+  return (c->bkind[s] == DG2_BC_INFLOW_Q || c->bkind[s] == DG2_BC_LEVEL) && c->nhyd[s] > 0 &&
+         c->hyd_kind[s] == c->bkind[s];
+}
+// A side's segment is not a plain wall.
+inline bool side_active(const dg2_ctx *c, int s) { return side_table_on(c, s) || c->bkind[s] == DG2_BC_OPEN; }
+
 constexpr int kDiagBlocks = 1024;  // partial sums of the diagnostics reduction
 
 inline char *plane(void *base, const dg2_ctx *c, int k) { return (char *)base + (size_t)k * c->P * c->esz; }
@@ -64,12 +73,13 @@ inline PlanArgs plan_args(const dg2_ctx *c) {
   p.rain_tb = c->rain_tb;
   p.rain_te = c->rain_te;
   for (int s = 0; s < 4; ++s) {
-    const bool on = c->inflow[s] && c->nhyd[s] > 0;
+    const bool on = side_table_on(c, s);
     p.nhyd[s] = on ? c->nhyd[s] : 0;
     p.hyd_t[s] = c->hyd_t[s];
     p.hyd_Q[s] = c->hyd_Q[s];
     const double d = (s == DG2_WEST || s == DG2_EAST) ? c->cfg.dy : c->cfg.dx;
-    p.seg_len[s] = on ? (c->seg_last[s] - c->seg_first[s] + 1) * d : 1.0;
+    // inflow tables give Q, turned into a unit discharge; level tables give eta
+    p.seg_len[s] = on && c->bkind[s] == DG2_BC_INFLOW_Q ? (c->seg_last[s] - c->seg_first[s] + 1) * d : 1.0;
   }
   p.ng = c->ng;
   p.gauge_cap = c->gcap > 0 ? c->gcap : 1;
@@ -97,7 +107,8 @@ inline Scen<real> scen(const dg2_ctx *c) {
   s.idx = (real)(1.0 / c->cfg.dx);
   s.idy = (real)(1.0 / c->cfg.dy);
   for (int k = 0; k < 4; ++k) {
-    const bool on = c->inflow[k] && c->nhyd[k] > 0;
+    const bool on = side_active(c, k);
+    s.bkind[k] = on ? c->bkind[k] : (int)DG2_BC_WALL;
     s.seg_first[k] = on ? c->seg_first[k] : 1;
     s.seg_last[k] = on ? c->seg_last[k] : 0;
   }

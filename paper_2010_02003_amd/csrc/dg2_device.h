@@ -22,7 +22,7 @@ struct Ctrl {
   double dt;           // size of the pending step, <= 0: idle
   double t_end;        // run-to target, +inf when none
   double rain;         // rain depth added by the pending step
-  double qin[4][2];    // unit inflow per side at the two stage times
+  double qin[4][2];    // per side at the two stage times: unit inflow, or water level
   double cflmin;       // min_c m_c of the current state (+inf: nothing wet)
   double last_dt;      // size of the last completed step
   long long step;      // completed steps
@@ -177,6 +177,9 @@ __device__ __forceinline__ void roe(real hL, real uL, real vL, real hR, real uR,
 // The two-argument face flux, chosen at compile time.
 enum : int { kFluxHLL = 0, kFluxRoe = 1 };
 
+// Boundary kinds of a side's segment (the values of dg2_bc).
+enum : int { kBcWall = 0, kBcInflow = 1, kBcLevel = 2, kBcOpen = 3 };
+
 template <int FLUX, typename real>
 __device__ __forceinline__ void face_flux(real hL, real uL, real vL, real hR, real uR, real vR,
                                           real g, real tol, real &F0, real &F1, real &F2) {
@@ -184,6 +187,38 @@ __device__ __forceinline__ void face_flux(real hL, real uL, real vL, real hR, re
     roe(hL, uL, vL, hR, uR, vR, g, tol, F0, F1, F2);
   else
     hll(hL, uL, vL, hR, uR, vR, g, tol, F0, F1, F2);
+}
+
+// Flux through a water-level or open boundary face, along the face normal.
+// (h, un, ut) is the inside dummy limit at the face, (hm, qnm, qtm) the
+// inside cell's mean state, zf the bed at the face and eta the prescribed
+// level; inside_plus: the inside lies on the + side (west and south faces).
+// Level: ghost depth max(0, eta - zf), normal velocity keeping the outgoing
+// Riemann invariant (u - 2c inside a west/south face, u + 2c inside an
+// east/north face), an inflow capped at the critical speed, tangential
+// velocity zero where the ghost's flow enters the domain, else from inside.
+// Open: the ghost holds the inside cell's mean state.
+template <int FLUX, typename real>
+__device__ __forceinline__ void ghost_face_flux(int kind, bool inside_plus, real eta, real zf,
+                                                real h, real un, real ut, real hm, real qnm,
+                                                real qtm, real g, real tol, real &F0, real &Fn,
+                                                real &Ft) {
+  real hg, ug, vg;
+  if (kind == kBcLevel) {
+    hg = dmax(real(0), eta - zf);
+    const real cg = dsqrt(g * hg), ci = dsqrt(g * h);
+    ug = inside_plus ? dmin(un - real(2) * ci + real(2) * cg, cg)
+                     : dmax(un + real(2) * ci - real(2) * cg, -cg);
+    // reservoir water enters without tangential motion; leaving water keeps its own
+    const bool entering = inside_plus ? ug > real(0) : ug < real(0);
+    vg = entering ? real(0) : ut;
+  } else {
+    dummy_limit(hm, qnm, qtm, tol, hg, ug, vg);
+  }
+  if (inside_plus)
+    face_flux<FLUX>(hg, ug, vg, h, un, ut, g, tol, F0, Fn, Ft);
+  else
+    face_flux<FLUX>(h, un, ut, hg, ug, vg, g, tol, F0, Fn, Ft);
 }
 
 // Prescribed discharge q through an inflow face: normal flux components

@@ -23,7 +23,8 @@ struct Scen {
   int nx, ny;
   long long P;
   real dx, dy, idx, idy;
-  int seg_first[4], seg_last[4];  // inflow segment per side (first > last: none)
+  int bkind[4];                   // boundary kind of each side's segment (dg2_bc)
+  int seg_first[4], seg_last[4];  // that segment (first > last: none)
   // gauges
   int ng;
   const int *g_cell;

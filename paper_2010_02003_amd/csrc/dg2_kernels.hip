@@ -94,42 +94,110 @@ __device__ __forceinline__ void cell_operator(const Row<real> &cur, real FE0, re
   Lop[8] = m3y * ((GN2 + GS2) - (Gp2 + Gm2) + tg3 * D0 * zby);
 }
 
+// One side's boundary segment as a lane sees it: kind (kBc*), whether this
+// lane's current face lies on it, the stage value (unit discharge or level)
+// and, for a level, the bed at the face.
+template <typename real>
+struct Bface {
+  int kind;
+  bool on;
+  real val, zf;
+};
+
+// Bed value at the face of cell (j, i) on side 0..3 (W, E, S, N).
+template <typename real>
+__device__ __forceinline__ real face_bed(const Scen<real> &s, int j, int i, int side) {
+  const unsigned off = (unsigned)(j * s.nx + i) * (unsigned)sizeof(real);
+  const real z0 = ld_at(s.z, off);
+  const real z1 = ld_at(s.z + (side < 2 ? 1 : 2) * s.P, off);
+  return (side == 0 || side == 2) ? z0 - z1 : z0 + z1;
+}
+
+// Whether a side's segment is active at this stage: an inflow with zero
+// discharge is a wall.
+template <typename real>
+__device__ __forceinline__ bool side_on(int kind, real val) {
+  return kind == kBcInflow ? val != real(0) : (kind == kBcLevel || kind == kBcOpen);
+}
+
 // North face of a row (the y-face to the row above) as [mass, x-mom, y-mom];
-// an inflow segment on the north wall replaces the flux.  dN = max(0, -h_N^-)
+// a boundary segment on the north wall replaces the flux.  dN = max(0, -h_N^-)
 // for the wall revision of the bed at that face.
 template <int FLUX, typename real>
-__device__ __forceinline__ void north_face(const Row<real> &cur, const Row<real> &nxt, bool inflow,
-                                           real q, real g, real tol, real &G0, real &G1, real &G2,
-                                           real &dN) {
+__device__ __forceinline__ void north_face(const Row<real> &cur, const Row<real> &nxt,
+                                           const Bface<real> &b, real g, real tol, real &G0,
+                                           real &G1, real &G2, real &dN) {
   y_face<FLUX>(cur, nxt, g, tol, G0, G1, G2);
   dN = dmax(real(0), -cur.nr);
-  if (inflow) {
-    inflow_flux(q, cur.nh, g, G0, G2);
-    G0 = -G0;
-    G1 = real(0);
+  if (b.on) {
+    if (b.kind == kBcInflow) {
+      inflow_flux(b.val, cur.nh, g, G0, G2);
+      G0 = -G0;
+      G1 = real(0);
+    } else {
+      real fn, ft;
+      ghost_face_flux<FLUX>(b.kind, false, b.val, b.zf, cur.nh, cur.nv, cur.nu, cur.W[0], cur.W[6],
+                            cur.W[3], g, tol, G0, fn, ft);
+      G1 = ft;
+      G2 = fn;
+    }
+  }
+}
+
+// South face of a row (the y-face to the row below, lo); a boundary segment
+// on the south wall replaces the flux.  dS = max(0, -h_N^- of lo).
+template <int FLUX, typename real>
+__device__ __forceinline__ void south_face(const Row<real> &lo, const Row<real> &cur,
+                                           const Bface<real> &b, real g, real tol, real &G0,
+                                           real &G1, real &G2, real &dS) {
+  y_face<FLUX>(lo, cur, g, tol, G0, G1, G2);
+  dS = dmax(real(0), -lo.nr);
+  if (b.on) {
+    if (b.kind == kBcInflow) {
+      inflow_flux(b.val, cur.sh, g, G0, G2);
+      G1 = real(0);
+    } else {
+      real fn, ft;
+      ghost_face_flux<FLUX>(b.kind, true, b.val, b.zf, cur.sh, cur.sv, cur.su, cur.W[0], cur.W[6],
+                            cur.W[3], g, tol, G0, fn, ft);
+      G1 = ft;
+      G2 = fn;
+    }
   }
 }
 
 // East face of every lane's cell (with the '+' limit of the lane to the east)
-// and its west face (the east face of the lane to the west), with inflow
-// segments on the west and east walls, and the wall-revision depths.
+// and its west face (the east face of the lane to the west), with boundary
+// segments on the west and east walls, and the wall-revision depths.  On
+// the west wall the face is computed by the ghost lane west of the domain,
+// whose row is the mirror image of the first cell (mean qx negated).
 template <int FLUX, typename real>
-__device__ __forceinline__ void east_west_faces(const Row<real> &cur, bool inW, real qW, bool inE,
-                                                real qE, real g, real tol, real &FE0, real &FE1,
-                                                real &FE2, real &FW0, real &FW1, real &FW2,
-                                                real &dE, real &dW) {
+__device__ __forceinline__ void east_west_faces(const Row<real> &cur, const Bface<real> &bW,
+                                                const Bface<real> &bE, real g, real tol, real &FE0,
+                                                real &FE1, real &FE2, real &FW0, real &FW1,
+                                                real &FW2, real &dE, real &dW) {
   const real ph = __shfl_down(cur.wh, 1, 64);
   const real pu = __shfl_down(cur.wu, 1, 64);
   const real pv = __shfl_down(cur.wv, 1, 64);
   face_flux<FLUX>(cur.eh, cur.eu, cur.ev, ph, pu, pv, g, tol, FE0, FE1, FE2);
-  if (inW) {
-    inflow_flux(qW, ph, g, FE0, FE1);
-    FE2 = real(0);
+  if (bW.on) {
+    if (bW.kind == kBcInflow) {
+      inflow_flux(bW.val, ph, g, FE0, FE1);
+      FE2 = real(0);
+    } else {
+      ghost_face_flux<FLUX>(bW.kind, true, bW.val, bW.zf, ph, pu, pv, cur.W[0], -cur.W[3], cur.W[6],
+                            g, tol, FE0, FE1, FE2);
+    }
   }
-  if (inE) {
-    inflow_flux(qE, cur.eh, g, FE0, FE1);
-    FE0 = -FE0;
-    FE2 = real(0);
+  if (bE.on) {
+    if (bE.kind == kBcInflow) {
+      inflow_flux(bE.val, cur.eh, g, FE0, FE1);
+      FE0 = -FE0;
+      FE2 = real(0);
+    } else {
+      ghost_face_flux<FLUX>(bE.kind, false, bE.val, bE.zf, cur.eh, cur.eu, cur.ev, cur.W[0], cur.W[3],
+                            cur.W[6], g, tol, FE0, FE1, FE2);
+    }
   }
   dE = dmax(real(0), -cur.er);
   FW0 = __shfl_up(FE0, 1, 64);
@@ -283,10 +351,11 @@ __device__ __forceinline__ void march_nl_dir(const Scen<real> &s, const Consts &
   const int si = STAGE - 1;
   const real qW = (real)s.ctrl->qin[0][si], qE = (real)s.ctrl->qin[1][si];
   const real qS = (real)s.ctrl->qin[2][si], qN = (real)s.ctrl->qin[3][si];
-  const bool faceW = (i == -1) && qW != real(0);
-  const bool faceE = (i == s.nx - 1) && qE != real(0);
-  const bool colS = qS != real(0) && i >= s.seg_first[2] && i <= s.seg_last[2];
-  const bool colN = qN != real(0) && i >= s.seg_first[3] && i <= s.seg_last[3];
+  const int kW = s.bkind[0], kE = s.bkind[1], kS = s.bkind[2], kN = s.bkind[3];
+  const bool faceW = (i == -1) && side_on(kW, qW);
+  const bool faceE = (i == s.nx - 1) && side_on(kE, qE);
+  const bool colS = side_on(kS, qS) && i >= s.seg_first[2] && i <= s.seg_last[2];
+  const bool colN = side_on(kN, qN) && i >= s.seg_first[3] && i <= s.seg_last[3];
 
   // gauges owned by this wavefront
   unsigned long long gmask = 0;
@@ -308,14 +377,13 @@ __device__ __forceinline__ void march_nl_dir(const Scen<real> &s, const Consts &
     load_raw<real, STAGE>(s, src, jfirst + d, ci, rawA);
     build_row<real, STAGE>(rawN, jfirst, s.ny, mx, rain, gdt, tol, cur);
     if (!down) {
-      y_face<FLUX>(back, cur, g, tol, CF0, CF1, CF2);
-      dC = dmax(real(0), -back.nr);
-      if (jfirst == 0 && colS) {
-        inflow_flux(qS, cur.sh, g, CF0, CF2);
-        CF1 = real(0);
-      }
+      const bool on = jfirst == 0 && colS;
+      const Bface<real> bS{kS, on, qS, on && kS == kBcLevel ? face_bed(s, 0, i, 2) : real(0)};
+      south_face<FLUX>(back, cur, bS, g, tol, CF0, CF1, CF2, dC);
     } else {
-      north_face<FLUX>(cur, back, jfirst == s.ny - 1 && colN, qN, g, tol, CF0, CF1, CF2, dC);
+      const bool on = jfirst == s.ny - 1 && colN;
+      const Bface<real> bN{kN, on, qN, on && kN == kBcLevel ? face_bed(s, s.ny - 1, i, 3) : real(0)};
+      north_face<FLUX>(cur, back, bN, g, tol, CF0, CF1, CF2, dC);
     }
   }
 
@@ -331,27 +399,28 @@ __device__ __forceinline__ void march_nl_dir(const Scen<real> &s, const Consts &
 
     real GN0, GN1, GN2, dN, GS0, GS1, GS2, dS;
     if (!down) {
-      north_face<FLUX>(cur, nxt, j == s.ny - 1 && colN, qN, g, tol, GN0, GN1, GN2, dN);
+      const bool on = j == s.ny - 1 && colN;
+      const Bface<real> bN{kN, on, qN, on && kN == kBcLevel ? face_bed(s, s.ny - 1, i, 3) : real(0)};
+      north_face<FLUX>(cur, nxt, bN, g, tol, GN0, GN1, GN2, dN);
       GS0 = CF0;
       GS1 = CF1;
       GS2 = CF2;
       dS = dC;
     } else {
-      y_face<FLUX>(nxt, cur, g, tol, GS0, GS1, GS2);
-      dS = dmax(real(0), -nxt.nr);
-      if (j == 0 && colS) {
-        inflow_flux(qS, cur.sh, g, GS0, GS2);
-        GS1 = real(0);
-      }
+      const bool on = j == 0 && colS;
+      const Bface<real> bS{kS, on, qS, on && kS == kBcLevel ? face_bed(s, 0, i, 2) : real(0)};
+      south_face<FLUX>(nxt, cur, bS, g, tol, GS0, GS1, GS2, dS);
       GN0 = CF0;
       GN1 = CF1;
       GN2 = CF2;
       dN = dC;
     }
     real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
-    east_west_faces<FLUX>(cur, faceW && j >= s.seg_first[0] && j <= s.seg_last[0], qW,
-                    faceE && j >= s.seg_first[1] && j <= s.seg_last[1], qE, g, tol, FE0, FE1, FE2,
-                    FW0, FW1, FW2, dE, dW);
+    const bool onW = faceW && j >= s.seg_first[0] && j <= s.seg_last[0];
+    const bool onE = faceE && j >= s.seg_first[1] && j <= s.seg_last[1];
+    const Bface<real> bW{kW, onW, qW, onW && kW == kBcLevel ? face_bed(s, j, 0, 0) : real(0)};
+    const Bface<real> bE{kE, onE, qE, onE && kE == kBcLevel ? face_bed(s, j, s.nx - 1, 1) : real(0)};
+    east_west_faces<FLUX>(cur, bW, bE, g, tol, FE0, FE1, FE2, FW0, FW1, FW2, dE, dW);
 
     if (own) {
       const long long cidx = (long long)j * s.nx + i;
@@ -588,10 +657,11 @@ __device__ __forceinline__ void march_ll(const Scen<real> &s, const Consts &c, i
   const int si = STAGE - 1;
   const real qW = (real)s.ctrl->qin[0][si], qE = (real)s.ctrl->qin[1][si];
   const real qS = (real)s.ctrl->qin[2][si], qN = (real)s.ctrl->qin[3][si];
-  const bool faceW = (i == -1) && qW != real(0);
-  const bool faceE = (i == s.nx - 1) && qE != real(0);
-  const bool colS = qS != real(0) && i >= s.seg_first[2] && i <= s.seg_last[2];
-  const bool colN = qN != real(0) && i >= s.seg_first[3] && i <= s.seg_last[3];
+  const int kW = s.bkind[0], kE = s.bkind[1], kS = s.bkind[2], kN = s.bkind[3];
+  const bool faceW = (i == -1) && side_on(kW, qW);
+  const bool faceE = (i == s.nx - 1) && side_on(kE, qE);
+  const bool colS = side_on(kS, qS) && i >= s.seg_first[2] && i <= s.seg_last[2];
+  const bool colN = side_on(kN, qN) && i >= s.seg_first[3] && i <= s.seg_last[3];
 
   unsigned long long gmask = 0;
   long long gslot = 0;
@@ -612,12 +682,9 @@ __device__ __forceinline__ void march_ll(const Scen<real> &s, const Consts &c, i
     load_row_ll<real, STAGE>(s, src, j0 + 1, ci, mx, rain, gdt, tol, rc);
     limited_row(rz, ra, rb, thx, thy, tol, prev);
     limited_row(ra, rb, rc, thx, thy, tol, cur);
-    y_face<FLUX>(prev, cur, g, tol, GS0, GS1, GS2);
-    dS = dmax(real(0), -prev.nr);
-    if (j0 == 0 && colS) {
-      inflow_flux(qS, cur.sh, g, GS0, GS2);
-      GS1 = real(0);
-    }
+    const bool on = j0 == 0 && colS;
+    const Bface<real> bS{kS, on, qS, on && kS == kBcLevel ? face_bed(s, 0, i, 2) : real(0)};
+    south_face<FLUX>(prev, cur, bS, g, tol, GS0, GS1, GS2, dS);
   }
 
   double mloc = __longlong_as_double((long long)kInfBits);
@@ -637,11 +704,15 @@ __device__ __forceinline__ void march_ll(const Scen<real> &s, const Consts &c, i
     limited_row(rb, rc, rd, thx, thy, tol, nxt);
 
     real GN0, GN1, GN2, dN;
-    north_face<FLUX>(cur, nxt, j == s.ny - 1 && colN, qN, g, tol, GN0, GN1, GN2, dN);
+    const bool onN = j == s.ny - 1 && colN;
+    const Bface<real> bN{kN, onN, qN, onN && kN == kBcLevel ? face_bed(s, s.ny - 1, i, 3) : real(0)};
+    north_face<FLUX>(cur, nxt, bN, g, tol, GN0, GN1, GN2, dN);
     real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
-    east_west_faces<FLUX>(cur, faceW && j >= s.seg_first[0] && j <= s.seg_last[0], qW,
-                    faceE && j >= s.seg_first[1] && j <= s.seg_last[1], qE, g, tol, FE0, FE1, FE2,
-                    FW0, FW1, FW2, dE, dW);
+    const bool onW = faceW && j >= s.seg_first[0] && j <= s.seg_last[0];
+    const bool onE = faceE && j >= s.seg_first[1] && j <= s.seg_last[1];
+    const Bface<real> bW{kW, onW, qW, onW && kW == kBcLevel ? face_bed(s, j, 0, 0) : real(0)};
+    const Bface<real> bE{kE, onE, qE, onE && kE == kBcLevel ? face_bed(s, j, s.nx - 1, 1) : real(0)};
+    east_west_faces<FLUX>(cur, bW, bE, g, tol, FE0, FE1, FE2, FW0, FW1, FW2, dE, dW);
 
     if (own) {
       real Lop[9];

@@ -25,7 +25,7 @@ LIB_PATH = os.environ.get("DG2_LIBRARY", os.path.join(_HERE, "libdg2.so"))
 FP64, FP32 = 0, 1
 NL, LL = 0, 1
 WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
-BC_WALL, BC_INFLOW_Q = 0, 1
+BC_WALL, BC_INFLOW_Q, BC_LEVEL, BC_OPEN = 0, 1, 2, 3
 FLUX_HLL, FLUX_ROE = 0, 1
 
 _STATUS = {0: "DG2_OK", -1: "DG2_EINVAL", -2: "DG2_ENOMEM", -3: "DG2_EHIP", -4: "DG2_ESTATE",
@@ -63,6 +63,8 @@ _SIGS = {
     "dg2_set_boundary": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32]),
     "dg2_set_inflow_hydrograph": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double),
                                             c_int32]),
+    "dg2_set_level_hydrograph": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double),
+                                           c_int32]),
     "dg2_set_rainfall": (c_int32, [c_void_p, c_double, c_double, c_double]),
     "dg2_set_gauges": (c_int32, [c_void_p, POINTER(c_double), c_int32, c_int32]),
     "dg2_set_fixed_dt": (c_int32, [c_void_p, c_double]),
@@ -228,6 +230,11 @@ class Sim:
         Q = _f64(Q)
         self._check(self._lib.dg2_set_inflow_hydrograph(self._ctx, side, _dp(t), _dp(Q), len(t)))
 
+    def set_level_hydrograph(self, side: int, t, eta):
+        t = _f64(t)
+        eta = _f64(eta)
+        self._check(self._lib.dg2_set_level_hydrograph(self._ctx, side, _dp(t), _dp(eta), len(t)))
+
     def set_rainfall(self, rate: float, t_begin: float, t_end: float):
         self._check(self._lib.dg2_set_rainfall(self._ctx, rate, t_begin, t_end))
 
@@ -277,6 +284,17 @@ class Sim:
         m, e, h = c_double(), c_double(), c_double()
         self._check(self._lib.dg2_diagnostics(self._ctx, byref(m), byref(e), byref(h)))
         return m.value, e.value, h.value
+
+    def history(self, times):
+        """Run to each of the increasing times in turn and record the mass,
+        total energy (Eq. 11-12) and smallest mean depth there: an array
+        (len(times), 4) of t, mass, energy, min_h."""
+        out = np.empty((len(times), 4), dtype=np.float64)
+        for k, T in enumerate(times):
+            self.run_to(float(T))
+            out[k, 0] = self.time()[0]
+            out[k, 1:] = self.diagnostics()
+        return out
 
     def time_kernels(self, nsteps: int):
         a, b, w = c_double(), c_double(), c_double()
@@ -426,6 +444,11 @@ def sim_from_scenario(sc, stream=None, precision: Optional[str] = None,
     for b in sc.inflows:
         s.set_boundary(b.side, BC_INFLOW_Q, b.first, b.last)
         s.set_inflow_hydrograph(b.side, b.t, b.Q)
+    for b in sc.levels:
+        s.set_boundary(b.side, BC_LEVEL, b.first, b.last)
+        s.set_level_hydrograph(b.side, b.t, b.eta)
+    for side, first, last in sc.opens:
+        s.set_boundary(side, BC_OPEN, first, last)
     if sc.rain is not None:
         s.set_rainfall(*sc.rain)
     if sc.fixed_dt > 0:

@@ -1,0 +1,154 @@
+"""GPU parity of the water-level and open boundaries against the oracle:
+one step on random wet/dry modes with every boundary kind on the four
+sides (NL and LL, HLL and Roe), a level filling a dry channel (Ritter's
+fan), Stoker's waves leaving through open ends, a rising and falling level
+hydrograph over a bumpy floodplain, a lake at rest held by its own level,
+a uniform stream through open sides, and a batch of such scenarios bitwise
+equal to plain runs."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dg2_oracle as O
+from paper_2010_02003_amd import dg2
+from paper_2010_02003_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+F64 = torch.float64
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _close(gpu, ref, rtol, what):
+    scale = np.maximum(np.abs(ref).reshape(ref.shape[0], -1).max(axis=1), 1.0)
+    err = np.abs(gpu - ref).reshape(ref.shape[0], -1).max(axis=1) / scale
+    assert np.all(np.isfinite(gpu)), what
+    assert err.max() <= rtol, "%s: plane errors %s" % (what, err)
+    return err.max()
+
+
+@pytest.mark.parametrize("variant,flux", [("NL", "HLL"), ("NL", "ROE"), ("LL", "HLL")])
+def test_one_step_with_level_and_open_boundaries(variant, flux):
+    nx, ny, dx, dy, dt = 41, 33, 2.0, 1.5, 2e-3
+    modes, Z = WL.random_modes(nx, ny, seed=91, slope=1.2)
+    man = np.random.default_rng(5).uniform(0.0, 0.05, (ny, nx))
+    s = dg2.Sim(nx, ny, dx, dy, variant=variant, flux=flux, ll_threshold=1.0)
+    s.set_dem_corners(Z)
+    s.set_manning(man)
+    s.set_boundary(dg2.WEST, dg2.BC_LEVEL, 4, 20)
+    s.set_level_hydrograph(dg2.WEST, [0.0, 1.0], [0.6, 0.9])
+    s.set_boundary(dg2.NORTH, dg2.BC_LEVEL, 10, 38)
+    s.set_level_hydrograph(dg2.NORTH, [0.0], [-0.2])
+    s.set_boundary(dg2.EAST, dg2.BC_OPEN, 0, 32)
+    s.set_boundary(dg2.SOUTH, dg2.BC_OPEN, 3, 30)
+    s.set_state(modes, 0.0)
+    s.set_fixed_dt(dt)
+    s.step(1)
+    gpu = s.get_state()[0]
+    lev = [O.LevelBC(O.WEST, 4, 20, torch.tensor([0.0, 1.0], dtype=F64), torch.tensor([0.6, 0.9], dtype=F64)),
+           O.LevelBC(O.NORTH, 10, 38, torch.tensor([0.0], dtype=F64), torch.tensor([-0.2], dtype=F64))]
+    opens = [O.OpenBC(O.EAST, 0, 32), O.OpenBC(O.SOUTH, 3, 30)]
+    prm = O.Params(nx=nx, ny=ny, dx=dx, dy=dy, manning=O._t(man), fixed_dt=dt, variant=variant,
+                   theta=1.0, flux=flux, levels=lev, opens=opens)
+    ref = O.step(O.from_planes(modes), 0.0, O.bed_from_corners(Z), prm, dt)
+    _close(gpu, O.to_planes(ref), 1e-12, "one step, level and open boundaries")
+
+
+def _scenario_level_channel():
+    nx, ny, dx = 100, 4, 1.0
+    X, _ = WL.corner_xy(nx, ny, dx, dx)
+    Z = np.zeros_like(X)
+    sc = WL.Scenario(name="level_channel", nx=nx, ny=ny, dx=dx, dy=dx, Z=Z, surface=np.zeros_like(Z),
+                     is_eta=False, manning=0.0, dt_max=0.05)
+    sc.levels = [WL.Level(O.WEST, 0, ny - 1, np.array([0.0]), np.array([0.4]))]
+    return sc
+
+
+def _scenario_open_stoker():
+    nx, ny, dx, x0 = 80, 3, 0.5, 30.0
+    X, _ = WL.corner_xy(nx, ny, dx, dx, x0, 0.0)
+    Z = np.zeros_like(X)
+    sc = WL.Scenario(name="open_stoker", nx=nx, ny=ny, dx=dx, dy=dx, Z=Z,
+                     surface=np.where(X < 50.0, 1.0, 0.5), is_eta=True, manning=0.0, x0=x0)
+    sc.opens = [(O.WEST, 0, ny - 1), (O.EAST, 0, ny - 1)]
+    return sc
+
+
+def _scenario_level_floodplain():
+    nx, ny, dx = 60, 40, 5.0
+    X, Y = WL.corner_xy(nx, ny, dx, dx)
+    Z = WL.fbm_surface((ny + 1, nx + 1), 0.7, 2.0, 33) + 0.01 * X
+    sc = WL.Scenario(name="level_floodplain", nx=nx, ny=ny, dx=dx, dy=dx, Z=Z,
+                     surface=np.zeros_like(Z), is_eta=False, manning=0.03, dt_max=0.5)
+    eta0 = float(Z[:, 0].min())
+    sc.levels = [WL.Level(O.WEST, 5, 34, np.array([0.0, 60.0, 120.0]),
+                          np.array([eta0, eta0 + 1.5, eta0 + 0.2]))]
+    sc.opens = [(O.EAST, 0, ny - 1)]
+    return sc
+
+
+@pytest.mark.parametrize("make,T", [(_scenario_level_channel, 5.0), (_scenario_open_stoker, 8.0),
+                                    (_scenario_level_floodplain, 120.0)])
+def test_boundary_runs_match_oracle(make, T):
+    sc = make()
+    _say("boundary run", sc.name, "to", T)
+    s = dg2.sim_from_scenario(sc)
+    s.run_to(T)
+    gpu, t, step, _ = s.get_state()
+    U, bed, prm = O.setup(sc)
+    r = O.run(U, bed, prm, t_end=T)
+    _say("  steps gpu %d oracle %d, max |dh0| %.2e" % (step, r.steps, np.abs(gpu[0] - r.U[0, 0].numpy()).max()))
+    assert t == T and step == r.steps
+    _close(gpu, O.to_planes(r.U), 1e-10, sc.name)
+
+
+def test_level_boundary_keeps_a_lake_at_rest():
+    sc = WL.dambreak_bump(nx=40, ny=30)
+    sc.surface = np.full_like(sc.Z, 1.0)
+    sc.levels = [WL.Level(O.WEST, 0, 29, np.array([0.0]), np.array([1.0])),
+                 WL.Level(O.SOUTH, 5, 30, np.array([0.0]), np.array([1.0]))]
+    s = dg2.sim_from_scenario(sc)
+    s.step(200)
+    st = s.get_state()[0]
+    assert np.abs(st[3:]).max() < 1e-12
+    U0 = O.to_planes(O.initial_state(sc.Z, sc.surface, True))
+    assert np.abs(st[0] - U0[0]).max() < 1e-12
+
+
+def test_uniform_flow_passes_through_open_boundaries():
+    nx, ny = 37, 21
+    X, _ = WL.corner_xy(nx, ny, 1.0, 1.0)
+    Z = np.zeros_like(X)
+    h, u, v = 0.8, 0.6, -0.3
+    sc = WL.Scenario(name="open_stream", nx=nx, ny=ny, dx=1.0, dy=1.0, Z=Z, surface=np.full_like(Z, h),
+                     is_eta=False, manning=0.0, qx=np.full_like(Z, h * u), qy=np.full_like(Z, h * v))
+    sc.opens = [(O.WEST, 0, ny - 1), (O.EAST, 0, ny - 1), (O.SOUTH, 0, nx - 1), (O.NORTH, 0, nx - 1)]
+    s = dg2.sim_from_scenario(sc)
+    U0 = s.get_state()[0]
+    assert abs(U0[3].mean() - h * u) < 1e-15 and abs(U0[6].mean() - h * v) < 1e-15
+    s.step(50)
+    assert np.abs(s.get_state()[0] - U0).max() < 1e-13
+
+
+def test_batch_with_level_and_open_boundaries_equals_plain_runs():
+    scs = [_scenario_level_channel(), _scenario_open_stoker(), _scenario_level_floodplain()]
+    sims = [dg2.sim_from_scenario(sc) for sc in scs]
+    batch = dg2.Batch(sims)
+    batch.step(80)
+    batch.sync()
+    for sc, a in zip(scs, sims):
+        b = dg2.sim_from_scenario(sc)
+        b.step(80)
+        assert np.array_equal(a.get_state()[0], b.get_state()[0]), sc.name
+    batch.close()
+
+
+def test_adjoint_rejects_level_and_open_boundaries():
+    sc = _scenario_level_channel()
+    s = dg2.sim_from_scenario(sc)
+    s.set_fixed_dt(0.01)
+    s.set_gauges([[3.0, 2.0]])
+    with pytest.raises(dg2.DG2Error):
+        dg2.Adjoint(s, 4, 2, -1, 0)

@@ -1,7 +1,8 @@
 """Thacker's curved oscillatory flow in a frictionless parabolic bowl (the
 long-run test of Sec. 2.3), on the GPU.
 
-* parity with the oracle over half a period (80 m cells, FP64);
+* parity with the oracle over half a period (80 m cells, FP64), with the
+  mass and energy histories (Eq. 11-12) at every eighth of the period;
 * the paper's long run on 40 m cells: depth against the exact solution at
   the maximally wet (7 tau/2) and maximally dry (8 tau) times the paper
   plots, and mass and total energy (Eq. 11-12) over 30 periods: mass to
@@ -28,14 +29,24 @@ def _say(*a):
 def test_thacker_matches_oracle_over_half_a_period():
     sc = WL.thacker_bowl(dx=80.0)
     s = dg2.sim_from_scenario(sc)
-    s.run_to(TAU / 2)
+    times = [TAU / 8, TAU / 4, 3 * TAU / 8, TAU / 2]
+    hist = s.history(times)
     gpu, t, step, _ = s.get_state()
     U, bed, prm = O.setup(sc)
-    r = O.run(U, bed, prm, t_end=TAU / 2)
-    dh = np.abs(gpu[0] - r.U[0, 0].numpy()).max()
-    _say("Thacker 80 m, tau/2: steps gpu %d oracle %d, max |dh0| %.2e" % (step, r.steps, dh))
-    assert t == TAU / 2 and step == r.steps
-    ref = O.to_planes(r.U)
+    t0, n = 0.0, 0
+    for k, T in enumerate(times):
+        r = O.run(U, bed, prm, t_end=T, t0=t0)
+        U, t0, n = r.U, r.t, n + r.steps
+        # mass and energy histories (Eq. 11-12) against the oracle's
+        assert hist[k, 0] == T
+        assert hist[k, 1] == pytest.approx(O.mass(U, prm), rel=1e-13)
+        assert hist[k, 2] == pytest.approx(O.energy(U, bed, prm), rel=1e-12)
+        assert hist[k, 3] == pytest.approx(float(U[0, 0].min()), abs=1e-12)
+    dh = np.abs(gpu[0] - U[0, 0].numpy()).max()
+    _say("Thacker 80 m, tau/2: steps gpu %d oracle %d, max |dh0| %.2e, energy / initial %.6f"
+         % (step, n, dh, hist[-1, 2] / hist[0, 2]))
+    assert t == TAU / 2 and step == n
+    ref = O.to_planes(U)
     scale = np.maximum(np.abs(ref).reshape(9, -1).max(axis=1), 1.0)
     assert (np.abs(gpu - ref).reshape(9, -1).max(axis=1) / scale).max() <= 1e-10
 
