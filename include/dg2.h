@@ -205,8 +205,9 @@ dg2_status dg2_diagnostics(dg2_ctx *ctx, double *mass, double *energy, double *m
 
 /* Time nsteps steps with HIP events on the context's stream, one event pair
  * per kernel: average milliseconds of the stage-1 kernel, the stage-2 kernel
- * and of a whole step (any pointer may be NULL).  The steps are real steps
- * of the simulation. */
+ * and of a whole step (any pointer may be NULL).  When the fused step kernel
+ * runs (dg2_set_step_kernel), *ms_stage1 is that kernel's time and
+ * *ms_stage2 is 0.  The steps are real steps of the simulation. */
 dg2_status dg2_time_kernels(dg2_ctx *ctx, int32_t nsteps, double *ms_stage1, double *ms_stage2,
                             double *ms_step);
 
@@ -214,6 +215,15 @@ dg2_status dg2_time_kernels(dg2_ctx *ctx, int32_t nsteps, double *ms_stage1, dou
  * wavefronts per workgroup (1, 2 or 4).  rows <= 0 restores the built-in
  * choice for this grid.  Results do not depend on it. */
 dg2_status dg2_set_launch(dg2_ctx *ctx, int32_t rows_per_wave, int32_t waves_per_block);
+
+/* How dg2_step runs the two RK stages of Sec. 2.1.2.  fused = 1 (default):
+ * one kernel per step that computes stage 1 a row ahead of stage 2 and keeps
+ * the stage-1 result in registers, so a step reads and writes the state once;
+ * it applies to DG2-NL in FP32 with the state in library memory (otherwise
+ * the per-stage kernels run).  fused = 0: one kernel per stage, with the stage-1
+ * result in a device buffer.  Results are bitwise the same.  DG2_EINVAL for
+ * other values. */
+dg2_status dg2_set_step_kernel(dg2_ctx *ctx, int32_t fused);
 
 /* Pick the launch shape by timing candidates on copies of the current state
  * (the state is restored afterwards); budget_ms bounds the time spent.  The
@@ -227,7 +237,9 @@ dg2_status dg2_state_layout(const dg2_ctx *ctx, size_t *bytes, size_t *plane_str
 /* Keep the state in caller-owned device memory (e.g. a torch tensor) of at
  * least dg2_state_layout bytes, 256-byte aligned.  The current state is
  * copied in; the buffer is borrowed and must outlive the context or the
- * next dg2_bind_device_state(ctx, NULL, 0), which returns to own memory. */
+ * next dg2_bind_device_state(ctx, NULL, 0), which returns to own memory.
+ * With a bound state dg2_step runs the per-stage kernels, which update the
+ * state in place (the fused step writes to a second buffer). */
 dg2_status dg2_bind_device_state(dg2_ctx *ctx, void *dev_ptr, size_t bytes);
 
 /* ------------------------------------------------------------------------
@@ -258,7 +270,9 @@ void dg2_batch_destroy(dg2_batch *b);
 const char *dg2_batch_last_error(const dg2_batch *b);
 
 /* Re-read the members' parameters (boundaries, hydrographs, rain, Manning,
- * fixed dt, gauges, bound state buffers). */
+ * fixed dt, gauges, bound state buffers).  A member's state buffer is also
+ * re-read by itself when it changed (a member stepped alone by the fused
+ * step kernel alternates between two buffers). */
 dg2_status dg2_batch_refresh(dg2_batch *b);
 
 /* Rows per wavefront (<= 0: built-in choice), wavefronts per workgroup (1, 2

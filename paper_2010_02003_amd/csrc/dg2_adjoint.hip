@@ -306,7 +306,7 @@ double *state(double *base, const dg2_adj *a, long long k) {
 hipError_t queue_fwd_step(dg2_adj *a, const Scen<double> &s1, const Scen<double> &s2,
                           const PlanArgs &pa) {
   const dg2_ctx *c = a->ctx;
-  const Launch L = launch_of(c);
+  const Launch L = stage_launch_of(c);
   hipError_t e = launch_stage<double>(1, DG2_NL, s1, consts(c), L, c->stream);
   if (e == hipSuccess) e = launch_stage<double>(2, DG2_NL, s2, consts(c), L, c->stream);
   if (e == hipSuccess) e = launch_plan(a->actrl, pa, kPlanFinishStep, 0.0, 0, c->stream);

@@ -19,8 +19,13 @@ struct dg2_ctx {
   size_t esz = 8;
   long long P = 0;  // plane stride (elements)
   long long ncell = 0;
+  // U: the state, U1: the stage buffer (stage-kernel path) or the next state
+  // (fused path, after which the two are swapped).  U_own and U1_own are the
+  // library's two allocations behind them; U may instead be a caller's buffer
+  // (dg2_bind_device_state), and then U1 is U1_own.
   void *U = nullptr, *U1 = nullptr, *W1 = nullptr, *z = nullptr, *n = nullptr;
-  void *U_own = nullptr;
+  void *U_own = nullptr, *U1_own = nullptr;
+  int fused_user = 1;  // dg2_set_step_kernel
   bool has_ncell = false;
   double n_uniform = 0.0;
   dg2::Ctrl *ctrl = nullptr;
@@ -131,8 +136,27 @@ inline Consts consts(const dg2_ctx *c) {
   return k;
 }
 
+// Both RK stages in one kernel: DG2-NL in FP32 with the state in library
+// memory.  (In FP64 the fused kernel needs more registers than three
+// wavefronts per SIMD allow and runs slower than the stage kernels.)
+inline bool fused_active(const dg2_ctx *c) {
+  return c->fused_user && c->f32 && c->cfg.variant == DG2_NL &&
+         (c->U == c->U_own || c->U == c->U1_own);
+}
+
+// Launch of the per-stage kernels, of the fused step kernel, and of whichever
+// dg2_step uses.
+inline Launch stage_launch_of(const dg2_ctx *c) {
+  return make_launch(c->cfg.nx, c->cfg.ny, c->cfg.variant == DG2_LL ? kStripLL : kStripNL,
+                     c->R_user, c->wpb_user, 34000);
+}
+// The fused kernel computes two halo rows of stage 1 per work item, so it
+// takes longer items (about three rounds of its ~3k resident wavefronts).
+inline Launch fused_launch_of(const dg2_ctx *c) {
+  return make_launch(c->cfg.nx, c->cfg.ny, kStripF, c->R_user, c->wpb_user, 8800);
+}
 inline Launch launch_of(const dg2_ctx *c) {
-  return make_launch(c->cfg.nx, c->cfg.ny, c->cfg.variant, c->R_user, c->wpb_user);
+  return fused_active(c) ? fused_launch_of(c) : stage_launch_of(c);
 }
 
 }  // namespace dg2

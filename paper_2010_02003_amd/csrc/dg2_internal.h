@@ -47,12 +47,20 @@ struct Launch {
 
 constexpr int kStripNL = 62;  // output columns per wavefront (halo 1)
 constexpr int kStripLL = 60;  // output columns per wavefront (halo 2)
+constexpr int kStripF = 60;   // fused NL step: output columns per wavefront (halo 2)
 
-Launch make_launch(int nx, int ny, int variant, int R, int wpb);
+// Work items of a launch over strips of `cols` output columns; R <= 0 picks
+// the built-in rows per wavefront, aiming at about `items` work items.
+Launch make_launch(int nx, int ny, int cols, int R, int wpb, int items);
 
 template <typename real>
 hipError_t launch_stage(int stage, int variant, const Scen<real> &s, const Consts &c,
                         const Launch &L, hipStream_t st);
+
+// Both RK stages of a DG2-NL step in one launch (FP32); writes s.Uout,
+// which must not alias s.U.
+template <typename real>
+hipError_t launch_fused(const Scen<real> &s, const Consts &c, const Launch &L, hipStream_t st);
 
 hipError_t launch_plan(Ctrl *ctrl, const PlanArgs &p, int mode, double t_end, int set_tend,
                        hipStream_t st);

@@ -501,10 +501,320 @@ __device__ __forceinline__ int stage_item(const Launch &L, int &item) {
 }
 
 template <typename real, int STAGE, int FLUX>
-__global__ void __launch_bounds__(256) k_stage_nl(Scen<real> s, Consts c, Launch L) {
+__global__ void __launch_bounds__(256, 2) k_stage_nl(Scen<real> s, Consts c, Launch L) {
   int item;
   if (!stage_item<STAGE>(L, item)) return;
   march_nl<real, STAGE, FLUX>(s, c, item % L.nstrips, item / L.nstrips, L.R, threadIdx.x & 63);
+}
+
+// ---------------------------------------------------------------------------
+// Fused DG2-NL step: both RK stages of Sec. 2.1.2 in one pass.
+//
+// A wavefront owns 60 output columns (lanes 2..61) and R output rows.  Stage
+// 1 marches one row ahead of stage 2 over the output rows and the row beyond
+// each end, on every lane; its result U1 stays in registers and feeds stage 2
+// of the row behind, which takes U1 of the rows on either side and of the
+// lanes on either side (valid on lanes 1..62).  A step thus reads a cell's
+// state, Manning value and bed slopes once (plus halos) and writes the new
+// state once, and U1 never goes to memory.  The new state goes to a second
+// buffer, since neighbouring wavefronts still read U^n; the host then swaps
+// the two.  Each cell is computed by the same device functions in the same
+// order as by the two stage kernels, so the results are bitwise equal.
+// ---------------------------------------------------------------------------
+
+// Face between row r of the march and the next row r + d (the north face of
+// r when marching up, its south face when marching down), with a boundary
+// segment where that face is the grid edge.
+template <int FLUX, bool down, typename real>
+__device__ __forceinline__ void face_ahead(const Scen<real> &s, int r, int i, const Row<real> &cur,
+                                           const Row<real> &nxt, bool colS, bool colN, real qS,
+                                           real qN, real g, real tol, real &F0, real &F1, real &F2,
+                                           real &dF) {
+  const int kS = s.bkind[2], kN = s.bkind[3];
+  if (!down) {
+    const bool on = r == s.ny - 1 && colN;
+    const Bface<real> b{kN, on, qN, on && kN == kBcLevel ? face_bed(s, s.ny - 1, i, 3) : real(0)};
+    north_face<FLUX>(cur, nxt, b, g, tol, F0, F1, F2, dF);
+  } else {
+    const bool on = r == 0 && colS;
+    const Bface<real> b{kS, on, qS, on && kS == kBcLevel ? face_bed(s, 0, i, 2) : real(0)};
+    south_face<FLUX>(nxt, cur, b, g, tol, F0, F1, F2, dF);
+  }
+}
+
+// Face between the previous row r - d (back) and row r.
+template <int FLUX, bool down, typename real>
+__device__ __forceinline__ void face_behind(const Scen<real> &s, int r, int i, const Row<real> &back,
+                                            const Row<real> &cur, bool colS, bool colN, real qS,
+                                            real qN, real g, real tol, real &F0, real &F1, real &F2,
+                                            real &dF) {
+  const int kS = s.bkind[2], kN = s.bkind[3];
+  if (!down) {
+    const bool on = r == 0 && colS;
+    const Bface<real> b{kS, on, qS, on && kS == kBcLevel ? face_bed(s, 0, i, 2) : real(0)};
+    south_face<FLUX>(back, cur, b, g, tol, F0, F1, F2, dF);
+  } else {
+    const bool on = r == s.ny - 1 && colN;
+    const Bface<real> b{kN, on, qN, on && kN == kBcLevel ? face_bed(s, s.ny - 1, i, 3) : real(0)};
+    north_face<FLUX>(cur, back, b, g, tol, F0, F1, F2, dF);
+  }
+}
+
+// East and west faces of row r in stage k (0 or 1) of the fused march.
+template <int FLUX, typename real>
+__device__ __forceinline__ void fused_x_faces(const Scen<real> &s, int r, const Row<real> &cur,
+                                              bool faceW, bool faceE, real qW, real qE, real g,
+                                              real tol, real &FE0, real &FE1, real &FE2, real &FW0,
+                                              real &FW1, real &FW2, real &dE, real &dW) {
+  const int kW = s.bkind[0], kE = s.bkind[1];
+  const bool onW = faceW && r >= s.seg_first[0] && r <= s.seg_last[0];
+  const bool onE = faceE && r >= s.seg_first[1] && r <= s.seg_last[1];
+  const Bface<real> bW{kW, onW, qW, onW && kW == kBcLevel ? face_bed(s, r, 0, 0) : real(0)};
+  const Bface<real> bE{kE, onE, qE, onE && kE == kBcLevel ? face_bed(s, r, s.nx - 1, 1) : real(0)};
+  east_west_faces<FLUX>(cur, bW, bE, g, tol, FE0, FE1, FE2, FW0, FW1, FW2, dE, dW);
+}
+
+// The row beyond the grid edge next to a row: its mirror image in y.
+template <typename real>
+__device__ __forceinline__ void ghost_row_y(const Row<real> &r, real tol, Row<real> &gh) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) gh.W[k] = r.W[k];
+  mirror(gh.W, false, true);
+  row_limits(gh, tol);
+}
+
+template <typename real, int FLUX, bool down>
+__device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Consts &c, int strip,
+                                                int seg, int R, int lane) {
+  const double dtd = s.ctrl->dt;
+  if (!(dtd > 0.0)) {
+    // an idle step (a run-to target was reached): the host swaps the two
+    // state buffers after every step, so the state is carried over unchanged
+    const int i = strip * kStripF + lane - 2;
+    if (lane >= 2 && lane <= kStripF + 1 && i < s.nx) {
+      for (int j = seg * R; j < min(seg * R + R, s.ny); ++j) {
+        const unsigned off = (unsigned)(j * s.nx + i) * (unsigned)sizeof(real);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) st_at(s.Uout + k * s.P, off, ld_at(s.U + k * s.P, off));
+      }
+    }
+    return;
+  }
+
+  const real dt = (real)dtd, g = (real)c.g, tol = (real)c.tol;
+  const real half = real(0.5);
+  const int ny = s.ny;
+  const int i = strip * kStripF + lane - 2;
+  const int j0 = seg * R, j1 = min(j0 + R, ny);
+  const int d = down ? -1 : 1;
+  const int jfirst = down ? j1 - 1 : j0, jlast = down ? j0 : j1 - 1;
+  // stage-1 rows: the output rows and the row beyond each end, inside the grid
+  const int afirst = min(max(jfirst - d, 0), ny - 1);
+  const int alast = min(max(jlast + d, 0), ny - 1);
+  const int astop = alast + d;
+  const bool own = lane >= 2 && lane <= kStripF + 1 && i < s.nx;
+  const int ci = i < 0 ? 0 : (i >= s.nx ? s.nx - 1 : i);
+  const bool mx = (i < 0) || (i >= s.nx);
+  // whether this strip holds the ghost lane west (i = -1) or east (i = nx) of the grid
+  const bool wedge = strip == 0;
+  const bool eedge = s.nx - strip * kStripF + 2 <= 63;
+  const real rain = (real)s.ctrl->rain;
+  const real gdt = g * dt;
+  const real *src = s.U;
+  real *dst = s.Uout;
+
+  // boundary segments of each stage (stage values of the unit discharge or level)
+  const int kW = s.bkind[0], kE = s.bkind[1], kS = s.bkind[2], kN = s.bkind[3];
+  const real qW1 = (real)s.ctrl->qin[0][0], qE1 = (real)s.ctrl->qin[1][0];
+  const real qS1 = (real)s.ctrl->qin[2][0], qN1 = (real)s.ctrl->qin[3][0];
+  const real qW2 = (real)s.ctrl->qin[0][1], qE2 = (real)s.ctrl->qin[1][1];
+  const real qS2 = (real)s.ctrl->qin[2][1], qN2 = (real)s.ctrl->qin[3][1];
+  const bool inS = i >= s.seg_first[2] && i <= s.seg_last[2];
+  const bool inN = i >= s.seg_first[3] && i <= s.seg_last[3];
+  const bool faceW1 = (i == -1) && side_on(kW, qW1), faceW2 = (i == -1) && side_on(kW, qW2);
+  const bool faceE1 = (i == s.nx - 1) && side_on(kE, qE1);
+  const bool faceE2 = (i == s.nx - 1) && side_on(kE, qE2);
+  const bool colS1 = side_on(kS, qS1) && inS, colS2 = side_on(kS, qS2) && inS;
+  const bool colN1 = side_on(kN, qN1) && inN, colN2 = side_on(kN, qN2) && inN;
+
+  unsigned long long gmask = 0;
+  long long gslot = 0;
+  if (s.ng > 0) {
+    gmask = gauge_mask(s, strip * kStripF, kStripF, j0, j1);
+    gslot = (s.ctrl->gauge_written % s.g_cap) * s.ng;
+  }
+
+  // stage 1 march state: current row, raw planes of the next two rows, face behind
+  Row<real> curA;
+  Raw<real, 1> rawA, rawN;
+  real CA0, CA1, CA2, dCA;
+  {
+    Row<real> back;
+    load_raw<real, 1>(s, src, afirst - d, ci, rawA);
+    load_raw<real, 1>(s, src, afirst, ci, rawN);
+    build_row<real, 1>(rawA, afirst - d, ny, mx, rain, gdt, tol, back);
+    load_raw<real, 1>(s, src, afirst + d, ci, rawA);
+    build_row<real, 1>(rawN, afirst, ny, mx, rain, gdt, tol, curA);
+    face_behind<FLUX, down>(s, afirst, i, back, curA, colS1, colN1, qS1, qN1, g, tol, CA0, CA1, CA2,
+                            dCA);
+  }
+  // stage 2 state: U1 row behind, the face behind it, and its stage-1 input and bed slopes
+  Row<real> curB;
+  real CB0 = 0, CB1 = 0, CB2 = 0, dCB = 0;
+  real W1p[9];
+  real zxp = 0, zyp = 0;
+
+  double mloc = __longlong_as_double((long long)kInfBits);
+  unsigned flags = 0;
+
+  for (int r = afirst; r != astop; r += d) {
+    if (down ? (r - 2 >= alast - 1) : (r + 2 <= alast + 1))
+      load_raw<real, 1>(s, src, r + 2 * d, ci, rawN);
+    const unsigned offA = (unsigned)(r * s.nx + ci) * (unsigned)sizeof(real);
+    const real zx = ld_at(s.z + s.P, offA), zy = ld_at(s.z + 2 * s.P, offA);
+
+    // ---- stage 1 on row r ----
+    Row<real> nxtA;
+    build_row<real, 1>(rawA, r + d, ny, mx, rain, gdt, tol, nxtA);
+    real FA0, FA1, FA2, dFA;
+    face_ahead<FLUX, down>(s, r, i, curA, nxtA, colS1, colN1, qS1, qN1, g, tol, FA0, FA1, FA2, dFA);
+    real u1[9];
+    {
+      real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
+      fused_x_faces<FLUX>(s, r, curA, faceW1, faceE1, qW1, qE1, g, tol, FE0, FE1, FE2, FW0, FW1, FW2,
+                          dE, dW);
+      const real GN0 = down ? CA0 : FA0, GN1 = down ? CA1 : FA1, GN2 = down ? CA2 : FA2;
+      const real GS0 = down ? FA0 : CA0, GS1 = down ? FA1 : CA1, GS2 = down ? FA2 : CA2;
+      const real dN = down ? dCA : dFA, dS = down ? dFA : dCA;
+      real Lop[9];
+      cell_operator(curA, FE0, FE1, FE2, FW0, FW1, FW2, GN0, GN1, GN2, GS0, GS1, GS2,
+                    zx - half * dE + half * dW, zy - half * dN + half * dS, g, tol, s.idx, s.idy,
+                    Lop);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) u1[k] = curA.W[k] + dt * Lop[k];
+      (void)wet_dry_fix(u1, tol);
+    }
+    // ghost lanes beyond the grid take U1 of the edge column (mirrored when the row is built)
+    if (wedge) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const real v = __shfl_down(u1[k], 1, 64);
+        if (i == -1) u1[k] = v;
+      }
+    }
+    if (eedge) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const real v = __shfl_up(u1[k], 1, 64);
+        if (i == s.nx) u1[k] = v;
+      }
+    }
+
+    // ---- stage 2: U1 of row r arrives ----
+    Row<real> nxtB;
+    {
+      Raw<real, 2> rb;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) rb.W[k] = u1[k];
+      build_row<real, 2>(rb, r, ny, mx, rain, gdt, tol, nxtB);
+    }
+    if (r == afirst) {
+      if (afirst == jfirst) {
+        // the row before the first output row is beyond the grid edge
+        Row<real> gh;
+        ghost_row_y(nxtB, tol, gh);
+        face_behind<FLUX, down>(s, r, i, gh, nxtB, colS2, colN2, qS2, qN2, g, tol, CB0, CB1, CB2,
+                                dCB);
+      }
+    } else {
+      const int kB = r - d;
+      real FB0, FB1, FB2, dFB;
+      face_ahead<FLUX, down>(s, kB, i, curB, nxtB, colS2, colN2, qS2, qN2, g, tol, FB0, FB1, FB2,
+                             dFB);
+      if (kB >= j0 && kB < j1) {
+        // output row kB
+        real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
+        fused_x_faces<FLUX>(s, kB, curB, faceW2, faceE2, qW2, qE2, g, tol, FE0, FE1, FE2, FW0, FW1,
+                            FW2, dE, dW);
+        if (own) {
+          const real GN0 = down ? CB0 : FB0, GN1 = down ? CB1 : FB1, GN2 = down ? CB2 : FB2;
+          const real GS0 = down ? FB0 : CB0, GS1 = down ? FB1 : CB1, GS2 = down ? FB2 : CB2;
+          const real dN = down ? dCB : dFB, dS = down ? dFB : dCB;
+          real Lop[9];
+          cell_operator(curB, FE0, FE1, FE2, FW0, FW1, FW2, GN0, GN1, GN2, GS0, GS1, GS2,
+                        zxp - half * dE + half * dW, zyp - half * dN + half * dS, g, tol, s.idx,
+                        s.idy, Lop);
+          real o[9];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) o[k] = half * (W1p[k] + curB.W[k] + dt * Lop[k]);
+          (void)wet_dry_fix(o, tol);
+          const long long cidx = (long long)kB * s.nx + i;
+          const unsigned off = (unsigned)cidx * (unsigned)sizeof(real);
+#pragma unroll
+          for (int k = 0; k < 9; ++k) st_at(dst + k * s.P, off, o[k]);
+          new_state_checks(s, o, cidx, gmask, gslot, g, tol, mloc, flags);
+        }
+      }
+      CB0 = FB0;
+      CB1 = FB1;
+      CB2 = FB2;
+      dCB = dFB;
+    }
+    curB = nxtB;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) W1p[k] = curA.W[k];
+    zxp = zx;
+    zyp = zy;
+
+    curA = nxtA;
+    rawA = rawN;
+    CA0 = FA0;
+    CA1 = FA1;
+    CA2 = FA2;
+    dCA = dFA;
+  }
+
+  if (alast == jlast) {
+    // the row after the last output row is beyond the grid edge
+    Row<real> gh;
+    ghost_row_y(curB, tol, gh);
+    real FB0, FB1, FB2, dFB;
+    face_ahead<FLUX, down>(s, jlast, i, curB, gh, colS2, colN2, qS2, qN2, g, tol, FB0, FB1, FB2, dFB);
+    real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
+    fused_x_faces<FLUX>(s, jlast, curB, faceW2, faceE2, qW2, qE2, g, tol, FE0, FE1, FE2, FW0, FW1,
+                        FW2, dE, dW);
+    if (own) {
+      const real GN0 = down ? CB0 : FB0, GN1 = down ? CB1 : FB1, GN2 = down ? CB2 : FB2;
+      const real GS0 = down ? FB0 : CB0, GS1 = down ? FB1 : CB1, GS2 = down ? FB2 : CB2;
+      const real dN = down ? dCB : dFB, dS = down ? dFB : dCB;
+      real Lop[9];
+      cell_operator(curB, FE0, FE1, FE2, FW0, FW1, FW2, GN0, GN1, GN2, GS0, GS1, GS2,
+                    zxp - half * dE + half * dW, zyp - half * dN + half * dS, g, tol, s.idx, s.idy,
+                    Lop);
+      real o[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) o[k] = half * (W1p[k] + curB.W[k] + dt * Lop[k]);
+      (void)wet_dry_fix(o, tol);
+      const long long cidx = (long long)jlast * s.nx + i;
+      const unsigned off = (unsigned)cidx * (unsigned)sizeof(real);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) st_at(dst + k * s.P, off, o[k]);
+      new_state_checks(s, o, cidx, gmask, gslot, g, tol, mloc, flags);
+    }
+  }
+
+  publish_min(s, lane, mloc, flags);
+}
+
+template <typename real, int FLUX>
+__global__ void __launch_bounds__(256, 3) k_step_nl(Scen<real> s, Consts c, Launch L) {
+  int item;
+  if (!stage_item<2>(L, item)) return;
+  const int strip = item % L.nstrips, seg = item / L.nstrips;
+  if (seg & 1)
+    march_fused_dir<real, FLUX, true>(s, c, strip, seg, L.R, threadIdx.x & 63);
+  else
+    march_fused_dir<real, FLUX, false>(s, c, strip, seg, L.R, threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------------------
@@ -749,7 +1059,7 @@ __device__ __forceinline__ void march_ll(const Scen<real> &s, const Consts &c, i
 }
 
 template <typename real, int STAGE, int FLUX>
-__global__ void __launch_bounds__(256) k_stage_ll(Scen<real> s, Consts c, Launch L) {
+__global__ void __launch_bounds__(256, 2) k_stage_ll(Scen<real> s, Consts c, Launch L) {
   int item;
   if (!stage_item<STAGE>(L, item)) return;
   march_ll<real, STAGE, FLUX>(s, c, item % L.nstrips, item / L.nstrips, L.R, threadIdx.x & 63);
@@ -770,7 +1080,7 @@ struct Item {
 };
 
 template <typename real, int STAGE, int VARIANT, int FLUX>
-__global__ void __launch_bounds__(256) k_batch_stage(const Scen<real> *__restrict__ scens,
+__global__ void __launch_bounds__(256, 2) k_batch_stage(const Scen<real> *__restrict__ scens,
                                                      const Item *__restrict__ items, int nitems,
                                                      Consts c, int R, int wpb) {
   const int lane = threadIdx.x & 63;
@@ -972,15 +1282,14 @@ __global__ void __launch_bounds__(256) k_diag_final(const double *part, int nb, 
 // Launchers
 // ---------------------------------------------------------------------------
 
-Launch make_launch(int nx, int ny, int variant, int R, int wpb) {
+Launch make_launch(int nx, int ny, int cols, int R, int wpb, int items) {
   Launch L;
-  const int cols = variant == 1 ? kStripLL : kStripNL;
   L.nstrips = (nx + cols - 1) / cols;
   if (R <= 0) {
-    // aim at ~34k wavefronts: about ten rounds of the ~3k resident slots, so
-    // the last round is short; the halo rows are mostly L2 hits (the work
-    // items of one XCD are neighbours)
-    long long r = (long long)L.nstrips * ny / 34000;
+    // aim at `items` wavefronts (stage kernels: ~34k, about ten rounds of the
+    // ~3k resident slots, so the last round is short; the halo rows are
+    // mostly L2 hits, the work items of one XCD being neighbours)
+    long long r = (long long)L.nstrips * ny / items;
     R = (int)(r < 4 ? 4 : (r > 32 ? 32 : r));
   }
   if (R > ny) R = ny;
@@ -1016,6 +1325,17 @@ hipError_t launch_stage(int stage, int variant, const Scen<real> &s, const Const
     else
       queue_stage_kernel<real, 2, kFluxHLL>(variant, s, c, L, st);
   }
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_fused(const Scen<real> &s, const Consts &c, const Launch &L, hipStream_t st) {
+  const dim3 block(64 * L.wpb);
+  const dim3 grid((L.nitems + L.wpb - 1) / L.wpb);
+  if (c.flux == kFluxRoe)
+    hipLaunchKernelGGL((k_step_nl<real, kFluxRoe>), grid, block, 0, st, s, c, L);
+  else
+    hipLaunchKernelGGL((k_step_nl<real, kFluxHLL>), grid, block, 0, st, s, c, L);
   return hipGetLastError();
 }
 
@@ -1144,6 +1464,8 @@ template hipError_t launch_stage<double>(int, int, const Scen<double> &, const C
                                          const Launch &, hipStream_t);
 template hipError_t launch_stage<float>(int, int, const Scen<float> &, const Consts &,
                                         const Launch &, hipStream_t);
+template hipError_t launch_fused<float>(const Scen<float> &, const Consts &, const Launch &,
+                                        hipStream_t);
 template hipError_t launch_cfl<double>(const Scen<double> &, const Consts &, hipStream_t);
 template hipError_t launch_cfl<float>(const Scen<float> &, const Consts &, hipStream_t);
 template hipError_t launch_diag<double>(const Scen<double> &, const Consts &, double *, int,

@@ -77,6 +77,7 @@ _SIGS = {
     "dg2_time_kernels": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double),
                                    POINTER(c_double)]),
     "dg2_set_launch": (c_int32, [c_void_p, c_int32, c_int32]),
+    "dg2_set_step_kernel": (c_int32, [c_void_p, c_int32]),
     "dg2_autotune": (c_int32, [c_void_p, c_double, POINTER(c_int32)]),
     "dg2_state_layout": (c_int32, [c_void_p, POINTER(c_size_t), POINTER(c_size_t)]),
     "dg2_bind_device_state": (c_int32, [c_void_p, c_void_p, c_size_t]),
@@ -248,6 +249,9 @@ class Sim:
 
     def set_launch(self, rows_per_wave: int, waves_per_block: int = 4):
         self._check(self._lib.dg2_set_launch(self._ctx, rows_per_wave, waves_per_block))
+
+    def set_step_kernel(self, fused: bool):
+        self._check(self._lib.dg2_set_step_kernel(self._ctx, 1 if fused else 0))
 
     def autotune(self, budget_ms: float = 200.0) -> int:
         r = c_int32()
