@@ -49,11 +49,12 @@ PAPER_RUNTIMES = {
 
 
 def kernel_source_hash() -> str:
-    """Hash of the stage kernels' sources and build flags (traffic counters
-    recorded for another hash are stale)."""
+    """Hash of the kernels' sources, launch shapes, buffer layout and build
+    flags (traffic counters recorded for another hash are stale)."""
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2010_02003_amd")
-    for f in ("csrc/dg2_device.h", "csrc/dg2_kernels.hip", "csrc/dg2_internal.h", "build.py"):
+    for f in ("csrc/dg2_device.h", "csrc/dg2_kernels.hip", "csrc/dg2_internal.h", "csrc/dg2_ctx.h",
+              "csrc/dg2_api.hip", "build.py"):
         h.update(open(os.path.join(pkg, f), "rb").read())
     return h.hexdigest()[:16]
 
