@@ -249,7 +249,9 @@ dg2_status dg2_bind_device_state(dg2_ctx *ctx, void *dev_ptr, size_t bytes);
  * all members, and each scenario keeps its own device-resident time step,
  * time, inflows, rain and Courant minimum, exactly as if it were stepped
  * alone (results are bitwise those of dg2_step on each member).  Steps are
- * replayed from a captured HIP graph.
+ * replayed from a captured HIP graph.  When every member would step with the
+ * fused step kernel (dg2_set_step_kernel) the batch does too: one persistent
+ * launch per step over all members.
  * ------------------------------------------------------------------------ */
 typedef struct dg2_batch dg2_batch;
 
@@ -276,8 +278,10 @@ const char *dg2_batch_last_error(const dg2_batch *b);
 dg2_status dg2_batch_refresh(dg2_batch *b);
 
 /* Rows per wavefront (<= 0: built-in choice), wavefronts per workgroup (1, 2
- * or 4) and steps per captured graph (<= 1: no graph, eager launches).
- * Results do not depend on these. */
+ * or 4) and steps per captured graph (<= 1: no graph, eager launches; with
+ * the fused step kernel an odd count is rounded up, since each step switches
+ * the members between their two state buffers).  Results do not depend on
+ * these. */
 dg2_status dg2_batch_set_launch(dg2_batch *b, int32_t rows_per_wave, int32_t waves_per_block,
                                 int32_t graph_steps);
 

@@ -776,7 +776,14 @@ struct dg2_batch {
   unsigned *d_status = nullptr, *h_status = nullptr;
   int R = 0, R_user = 0, wpb = 4, graph_steps = 16;
   int blocks1 = 0, blocks2 = 0;
-  std::vector<void *> seenU;  // members' state buffers when the scenarios were uploaded
+  std::vector<void *> seenU;  // members' state buffers as the batch last left them
+  // fused step kernel: both RK stages per launch; each step writes every
+  // member's next state into its other buffer, using scenario table `par`
+  // (0: U -> U1, 1: U1 -> U as uploaded), and the host swaps the members'
+  // buffers after queueing it.  Graphs hold an even number of steps and are
+  // recaptured when they would start at the other parity.
+  bool fused = false;
+  int par = 0, graph_par = 0, blocksF = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::string err;
@@ -812,19 +819,24 @@ void drop_graph(dg2_batch *b) {
   b->graph = nullptr;
 }
 
-// Rows per wavefront: ~16k items over the whole batch, 4..32.
+int batch_cols(const dg2_batch *b) {
+  return b->fused ? kStripF : (b->variant == 1 ? kStripLL : kStripNL);
+}
+
+// Rows per wavefront: ~16k items over the whole batch (fused step: ~8.8k,
+// since each item also computes two halo rows of stage 1), 4..32.
 int batch_rows(const dg2_batch *b) {
   if (b->R_user > 0) return b->R_user;
-  const int cols = b->variant == 1 ? kStripLL : kStripNL;
+  const int cols = batch_cols(b);
   long long lanes_rows = 0;
   for (auto *c : b->m) lanes_rows += (long long)((c->cfg.nx + cols - 1) / cols) * c->cfg.ny;
-  long long r = lanes_rows / 16384;
+  long long r = lanes_rows / (b->fused ? 8800 : 16384);
   return (int)(r < 4 ? 4 : (r > 32 ? 32 : r));
 }
 
 dg2_status build_items(dg2_batch *b) {
   b->R = batch_rows(b);
-  const int cols = b->variant == 1 ? kStripLL : kStripNL;
+  const int cols = batch_cols(b);
   std::vector<BatchItem> items;
   for (size_t k = 0; k < b->m.size(); ++k) {
     const dg2_config &g = b->m[k]->cfg;
@@ -851,14 +863,28 @@ dg2_status upload_scens(dg2_batch *b) {
   std::vector<PlanArgs> pa;
   std::vector<Ctrl *> ctrls;
   for (auto *c : b->m) {
-    sc.push_back(scen<real>(c));
+    Scen<real> s = scen<real>(c);
+    if (b->fused) s.Uout = (real *)c->U1;
+    sc.push_back(s);
     pa.push_back(plan_args(c));
     ctrls.push_back(c->ctrl);
+  }
+  if (b->fused) {
+    // table 1: the buffers the other way round
+    for (auto *c : b->m) {
+      Scen<real> s = scen<real>(c);
+      s.U = (const real *)c->U1;
+      s.U1 = (real *)c->U;
+      s.Uout = (real *)c->U;
+      sc.push_back(s);
+    }
   }
   const size_t n = b->m.size();
   b->seenU.clear();
   for (auto *c : b->m) b->seenU.push_back(c->U);
-  BCHK(b, hipMemcpy(b->d_scens, sc.data(), n * sizeof(Scen<real>), hipMemcpyHostToDevice), "scenarios");
+  b->par = 0;
+  BCHK(b, hipMemcpy(b->d_scens, sc.data(), sc.size() * sizeof(Scen<real>), hipMemcpyHostToDevice),
+       "scenarios");
   BCHK(b, hipMemcpy(b->d_plan, pa.data(), n * sizeof(PlanArgs), hipMemcpyHostToDevice), "plans");
   BCHK(b, hipMemcpy(b->d_ctrls, ctrls.data(), n * sizeof(Ctrl *), hipMemcpyHostToDevice), "ctrls");
   return DG2_OK;
@@ -878,6 +904,19 @@ hipError_t batch_plan(dg2_batch *b, int mode, double t_end = 0.0, int set_tend =
 }
 
 dg2_status batch_queue_step(dg2_batch *b) {
+  if (b->fused) {
+    const Scen<float> *tab = (const Scen<float> *)b->d_scens + (size_t)b->par * b->m.size();
+    BCHK(b, launch_batch_fused(tab, b->d_items, b->nitems, b->consts, b->R, b->wpb, b->blocksF,
+                               b->stream),
+         "batch step");
+    BCHK(b, batch_plan(b, kPlanFinishStep), "batch plan");
+    b->par ^= 1;
+    for (size_t k = 0; k < b->m.size(); ++k) {
+      std::swap(b->m[k]->U, b->m[k]->U1);
+      b->seenU[k] = b->m[k]->U;
+    }
+    return DG2_OK;
+  }
   BCHK(b, batch_stage(b, 1), "batch stage 1");
   BCHK(b, batch_stage(b, 2), "batch stage 2");
   BCHK(b, batch_plan(b, kPlanFinishStep), "batch plan");
@@ -885,7 +924,9 @@ dg2_status batch_queue_step(dg2_batch *b) {
 }
 
 dg2_status ensure_graph(dg2_batch *b) {
+  if (b->gexec && b->fused && b->graph_par != b->par) drop_graph(b);
   if (b->gexec || b->graph_steps <= 1) return DG2_OK;
+  b->graph_par = b->par;
   BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "graph capture");
   dg2_status st = DG2_OK;
   for (int k = 0; k < b->graph_steps && st == DG2_OK; ++k) st = batch_queue_step(b);
@@ -941,10 +982,19 @@ dg2_status batch_status(dg2_batch *b, unsigned *active, unsigned *flags) {
 }
 
 dg2_status batch_setup(dg2_batch *b) {
+  b->fused = true;
+  for (auto *c : b->m) b->fused = b->fused && fused_active(c);
+  if (b->fused && b->graph_steps > 1 && (b->graph_steps & 1)) b->graph_steps += 1;
   dg2_status st = b->f32 ? upload_scens<float>(b) : upload_scens<double>(b);
   if (st != DG2_OK) return st;
   if ((st = build_items(b)) != DG2_OK) return st;
   const int fx = b->consts.flux;
+  if (b->fused) {
+    b->blocksF = batch_fused_blocks(fx, b->wpb);
+    const int need = (b->nitems + b->wpb - 1) / b->wpb;
+    if (b->blocksF > need) b->blocksF = need;
+    if (b->blocksF < 1) b->blocksF = 1;
+  }
   b->blocks1 = b->f32 ? batch_blocks<float>(1, b->variant, fx, b->wpb)
                       : batch_blocks<double>(1, b->variant, fx, b->wpb);
   b->blocks2 = b->f32 ? batch_blocks<float>(2, b->variant, fx, b->wpb)
@@ -1012,7 +1062,7 @@ dg2_status dg2_batch_create(dg2_ctx *const *members, int32_t n, void *hip_stream
     if (e != hipSuccess) return bail(bhip(b, e, "member sync"));
   }
   const size_t ssz = b->f32 ? sizeof(Scen<float>) : sizeof(Scen<double>);
-  if ((e = hipMalloc(&b->d_scens, n * ssz)) != hipSuccess) return bail(bhip(b, e, "scenarios"));
+  if ((e = hipMalloc(&b->d_scens, 2 * n * ssz)) != hipSuccess) return bail(bhip(b, e, "scenarios"));
   if ((e = hipMalloc((void **)&b->d_ctrls, n * sizeof(Ctrl *))) != hipSuccess) return bail(bhip(b, e, "ctrls"));
   if ((e = hipMalloc((void **)&b->d_plan, n * sizeof(PlanArgs))) != hipSuccess) return bail(bhip(b, e, "plans"));
   if ((e = hipMalloc((void **)&b->d_status, 2 * sizeof(unsigned))) != hipSuccess) return bail(bhip(b, e, "status"));

@@ -176,3 +176,32 @@ def test_step_kernel_switch_rejects_bad_values():
     s = dg2.Sim(8, 8, 1.0)
     with pytest.raises(dg2.DG2Error):
         s._check(s._lib.dg2_set_step_kernel(s._ctx, 2))
+
+
+def test_fused_batch_parity_graphs_and_run_to():
+    """A batch of FP32 members steps with the fused kernel too: every step
+    switches each member between its two state buffers, so graph replays,
+    eager remainders of odd length, an odd graph length and a run-to with
+    members idling at the target must all leave each member equal to the
+    member stepped alone."""
+    scs = WL.ensemble(5)
+    sims = [dg2.sim_from_scenario(sc) for sc in scs]
+    plain = [dg2.sim_from_scenario(sc) for sc in scs]
+    batch = dg2.Batch(sims)
+    batch.set_launch(0, 4, 5)  # odd graph length: rounded up to 6
+    for n in (7, 6, 1, 12, 3):
+        batch.step(n)
+        for p in plain:
+            p.step(n)
+        batch.sync()
+        for k in range(len(scs)):
+            _same(sims[k], plain[k], "member %d after %d more steps" % (k, n))
+    T = max(s.time()[0] for s in sims) + 2.5
+    batch.run_to(T)
+    batch.sync()
+    for p in plain:
+        p.run_to(T)
+    for k in range(len(scs)):
+        assert sims[k].time()[0] == T
+        _same(sims[k], plain[k], "member %d after run_to" % k)
+    batch.close()
