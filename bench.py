@@ -309,12 +309,14 @@ def main():
     b1, b2 = algorithmic_bytes(sc, esz)
     bf = fused_bytes(sc, esz)
     traffic = None
+    valu_busy = None
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     kname = "k_step_nl" if fused else "k_stage_nl"
     if os.path.exists(tfile):
         ent = json.load(open(tfile)).get(args.workload)
         if ent and ent.get("kernel_hash") == kernel_source_hash() and ent.get("kernel") == kname:
             traffic = ent.get("bytes_per_launch")
+            valu_busy = ent.get("valu_busy")
     real = "float" if esz == 4 else "double"
     if fused:
         ach = cells * bf / (ms1 * 1e-3) / 1e9
@@ -322,7 +324,10 @@ def main():
                 "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                 "traffic": traffic, "bytes_per_cell": bf, "ms_per_launch": ms1,
                 "step_frac": cells * bf / (wall / args.steps) / 1e9 / HBM_PEAK_GBS,
-                "ms_per_step_with_events": ms_step_ev}
+                "ms_per_step_with_events": ms_step_ev,
+                # the kernel is bound by vector-ALU issue, not HBM: the VALUBusy
+                # counter of the profiled run of these sources
+                "valu_busy": valu_busy}
         # the per-stage kernels on the same steps, for comparison
         sim.set_step_kernel(False)
         reset()
