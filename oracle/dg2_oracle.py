@@ -198,6 +198,9 @@ class Params:
     fixed_dt: float = 0.0
     x0: float = 0.0
     y0: float = 0.0
+    # stage-1 Courant check (an option, off by default): up to this many
+    # repeats of stage 1 with a smaller step when its result breaks Cr
+    stage_check: int = 0
 
 
 def _table_value(ts, vs, t: float):
@@ -677,18 +680,50 @@ def wet_dry_fix(U: torch.Tensor, tol: float) -> torch.Tensor:
     return out
 
 
-def step(U: torch.Tensor, t: float, bed: Bed, prm: Params, dt: float):
-    """One time step t -> t + dt: rain, friction, [LL], two RK2 stages."""
+def _stage1(U: torch.Tensor, t: float, bed: Bed, prm: Params, dt: float):
+    """Stage input W (rain, friction split, [LL]) and stage-1 result U1."""
     W = U.clone()
     W[H, M0] = W[H, M0] + rain_depth(prm, t, dt)
     W = apply_friction(W, prm.manning, dt, prm.g, prm.tol)
     if prm.variant == "LL":
         W = local_limit(W, bed, prm)
     U1 = wet_dry_fix(W + dt * spatial_operator(W, bed, prm, t), prm.tol)
+    return W, U1
+
+
+def _stage2(W: torch.Tensor, U1: torch.Tensor, t: float, bed: Bed, prm: Params, dt: float):
     if prm.variant == "LL":
         U1 = local_limit(U1, bed, prm)
     U2 = 0.5 * (W + U1 + dt * spatial_operator(U1, bed, prm, t + dt))
     return wet_dry_fix(U2, prm.tol)
+
+
+def step(U: torch.Tensor, t: float, bed: Bed, prm: Params, dt: float):
+    """One time step t -> t + dt: rain, friction, [LL], two RK2 stages."""
+    W, U1 = _stage1(U, t, bed, prm, dt)
+    return _stage2(W, U1, t, bed, prm, dt)
+
+
+def step_checked(U: torch.Tensor, t: float, bed: Bed, prm: Params, dt: float):
+    """A step whose stage-1 result also keeps the Courant number (an option).
+
+    The step size of Sec. 2.1.2 comes from the state at the start of the
+    step, but stage 1 can give a thin film on a steep bank tens of m/s, and
+    stage 2 then breaks the Courant bound that keeps depths positive.  Here
+    stage 1 is repeated (at most prm.stage_check times) with dt = Cr times the
+    Courant minimum of its own result while dt exceeds that; the last attempt
+    is kept.  With a fixed step size (or stage_check = 0) this is `step`.
+    Returns the new state and the step size used.
+    """
+    W, U1 = _stage1(U, t, bed, prm, dt)
+    if prm.fixed_dt <= 0.0:
+        for _ in range(prm.stage_check):
+            lim = prm.cfl * cfl_min(U1, prm)
+            if not (dt > lim):
+                break
+            dt = lim
+            W, U1 = _stage1(U, t, bed, prm, dt)
+    return _stage2(W, U1, t, bed, prm, dt), dt
 
 
 # ---------------------------------------------------------------------------
@@ -778,7 +813,10 @@ def run(U: torch.Tensor, bed: Bed, prm: Params, steps: Optional[int] = None,
             dt = time_step(U, prm, t, t_end)
         if dt <= 0.0:
             break
-        U = step(U, t, bed, prm, dt)
+        if prm.stage_check > 0:
+            U, dt = step_checked(U, t, bed, prm, dt)
+        else:
+            U = step(U, t, bed, prm, dt)
         t = t_end if (t_end - t) == dt else t + dt
         n += 1
         dts.append(dt)
@@ -798,7 +836,7 @@ def params_from_scenario(sc) -> Params:
     return Params(nx=sc.nx, ny=sc.ny, dx=sc.dx, dy=sc.dy, g=sc.g, tol=sc.tol_dry, cfl=sc.cfl,
                   dt_max=sc.dt_max, theta=sc.theta, variant=sc.variant, manning=man,
                   inflows=infl, levels=levs, opens=opens, rain=sc.rain, fixed_dt=sc.fixed_dt,
-                  x0=sc.x0, y0=sc.y0, flux=sc.flux)
+                  x0=sc.x0, y0=sc.y0, flux=sc.flux, stage_check=sc.stage_check)
 
 
 def setup(sc):

@@ -88,6 +88,7 @@ class Scenario:
     gauges: Optional[np.ndarray] = None  # (ng, 2) x, y in m
     x0: float = 0.0
     y0: float = 0.0
+    stage_check: int = 0  # repeats of stage 1 allowed by the stage-1 Courant check (0: off)
 
     @property
     def cells(self) -> int:
@@ -189,6 +190,23 @@ def floodplain(nx: int = 1024, ny: int = 512, dx: float = 2.0, variant: str = "N
                     surface=h, is_eta=False, manning=0.035, cfl=0.3, dt_max=1.0,
                     variant=variant, precision=precision, t_end=t_end, inflows=[inflow],
                     gauges=gauges)
+
+
+def floodplain_mouth(nx: int = 40, ny: int = 40, row0: int = 236, stage_check: int = 0,
+                     precision: str = "fp64") -> Scenario:
+    """The corner of the floodplain around its inflow mouth: columns 0..nx-1
+    and rows row0..row0+ny-1 of the 1024 x 512 grid, with the same bed (the
+    channel carved with 1 m steps across one cell), the same inflow (the
+    whole mouth segment lies inside) and walls on the cut edges."""
+    full = floodplain(precision=precision)
+    b = full.inflows[0]
+    assert row0 <= b.first and b.last < row0 + ny
+    Z = full.Z[row0:row0 + ny + 1, 0:nx + 1].copy()
+    return Scenario(name="floodplain_mouth_%dx%d" % (nx, ny), nx=nx, ny=ny, dx=full.dx, dy=full.dy, Z=Z,
+                    surface=np.zeros_like(Z), is_eta=False, manning=full.manning, cfl=full.cfl,
+                    dt_max=full.dt_max, precision=precision,
+                    inflows=[Inflow(b.side, b.first - row0, b.last - row0, b.t, b.Q)],
+                    y0=row0 * full.dy, stage_check=stage_check)
 
 
 def urban(n: int = 4096, dx: float = 0.5, nblocks: int = 2000, precision: str = "fp32",
