@@ -100,10 +100,37 @@ dg2_status download(dg2_ctx *c, double *dst, const void *src, size_t n) {
   return DG2_OK;
 }
 
-hipError_t queue_stage(dg2_ctx *c, int stage) {
+// A stage kernel on the context's buffers; ctrl != nullptr replaces the
+// context's control block (the repeat block of the stage-1 Courant check).
+hipError_t queue_stage(dg2_ctx *c, int stage, Ctrl *ctrl = nullptr) {
   const Launch L = stage_launch_of(c);
-  if (c->f32) return launch_stage<float>(stage, c->cfg.variant, scen<float>(c), consts(c), L, c->stream);
-  return launch_stage<double>(stage, c->cfg.variant, scen<double>(c), consts(c), L, c->stream);
+  if (c->f32) {
+    Scen<float> s = scen<float>(c);
+    if (ctrl) s.ctrl = ctrl;
+    return launch_stage<float>(stage, c->cfg.variant, s, consts(c), L, c->stream);
+  }
+  Scen<double> s = scen<double>(c);
+  if (ctrl) s.ctrl = ctrl;
+  return launch_stage<double>(stage, c->cfg.variant, s, consts(c), L, c->stream);
+}
+
+// Courant minimum of the stage-1 result into the repeat block, then the
+// check; attempt 0 follows the first stage 1, attempt k its k-th repeat.
+hipError_t queue_stage_check(dg2_ctx *c, int attempt) {
+  const Ctrl *gate = attempt == 0 ? nullptr : c->ctrl2;
+  hipError_t e;
+  if (c->f32) {
+    Scen<float> s = scen<float>(c);
+    s.U = (const float *)c->U1;
+    e = launch_cfl<float>(s, consts(c), c->stream, gate, &c->ctrl2->minbits);
+  } else {
+    Scen<double> s = scen<double>(c);
+    s.U = (const double *)c->U1;
+    e = launch_cfl<double>(s, consts(c), c->stream, gate, &c->ctrl2->minbits);
+  }
+  if (e != hipSuccess) return e;
+  return launch_stage_check(c->ctrl, c->ctrl2, plan_args(c), attempt == 0, attempt == c->stage_check,
+                            c->stream);
 }
 
 hipError_t queue_plan(dg2_ctx *c, int mode, double t_end = 0.0, int set_tend = 0) {
@@ -129,6 +156,15 @@ dg2_status queue_step(dg2_ctx *c, hipEvent_t *ev = nullptr) {
   }
   if (ev) HIPCHK(c, hipEventRecord(ev[0], c->stream), "event");
   HIPCHK(c, queue_stage(c, 1), "stage 1 launch");
+  if (c->stage_check > 0) {
+    // repeats of stage 1 with a smaller step; each returns at once unless
+    // the check before it armed the repeat block
+    HIPCHK(c, queue_stage_check(c, 0), "stage check launch");
+    for (int k = 1; k <= c->stage_check; ++k) {
+      HIPCHK(c, queue_stage(c, 1, c->ctrl2), "stage 1 repeat launch");
+      HIPCHK(c, queue_stage_check(c, k), "stage check launch");
+    }
+  }
   if (ev) HIPCHK(c, hipEventRecord(ev[1], c->stream), "event");
   HIPCHK(c, queue_stage(c, 2), "stage 2 launch");
   if (ev) HIPCHK(c, hipEventRecord(ev[2], c->stream), "event");
@@ -209,7 +245,7 @@ const char *dg2_last_error(const dg2_ctx *ctx) {
 void dg2_destroy(dg2_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  void *bufs[] = {c->U_own, c->U1_own, c->W1, c->z, c->n, c->ctrl, c->g_cell, c->g_xi,
+  void *bufs[] = {c->U_own, c->U1_own, c->W1, c->z, c->n, c->ctrl, c->ctrl2, c->g_cell, c->g_xi,
                   c->g_zeta, c->g_z, c->g_buf, c->g_t, c->diag_part, c->diag_out};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
@@ -272,6 +308,13 @@ dg2_status dg2_create(const dg2_config *cfg, dg2_ctx **out) {
   if (cfg->variant == DG2_LL && (s = alloc(c, &c->W1, 9 * pb, "limited stage input")) != DG2_OK)
     return bail(s);
   if ((s = alloc(c, (void **)&c->ctrl, sizeof(Ctrl), "ctrl")) != DG2_OK) return bail(s);
+  if ((s = alloc(c, (void **)&c->ctrl2, sizeof(Ctrl), "ctrl")) != DG2_OK) return bail(s);
+  {
+    Ctrl rep{};
+    rep.minbits = kInfBits;
+    e = hipMemcpy(c->ctrl2, &rep, sizeof(Ctrl), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(hipfail(c, e, "ctrl"));
+  }
   if ((s = alloc(c, (void **)&c->diag_part, kDiagBlocks * 4 * sizeof(double), "diag")) != DG2_OK)
     return bail(s);
   if ((s = alloc(c, (void **)&c->diag_out, 4 * sizeof(double), "diag")) != DG2_OK) return bail(s);
@@ -675,6 +718,13 @@ dg2_status dg2_time_kernels(dg2_ctx *c, int32_t nsteps, double *ms1, double *ms2
   return dg2_sync(c);
 }
 
+dg2_status dg2_set_stage_check(dg2_ctx *c, int32_t repeats) {
+  if (!c) return DG2_EINVAL;
+  if (repeats < 0 || repeats > 8) return fail(c, DG2_EINVAL, "repeats must be 0..8");
+  c->stage_check = repeats;
+  return DG2_OK;
+}
+
 dg2_status dg2_set_step_kernel(dg2_ctx *c, int32_t fused) {
   if (!c) return DG2_EINVAL;
   if (fused != 0 && fused != 1) return fail(c, DG2_EINVAL, "fused must be 0 or 1");
@@ -982,6 +1032,9 @@ dg2_status batch_status(dg2_batch *b, unsigned *active, unsigned *flags) {
 }
 
 dg2_status batch_setup(dg2_batch *b) {
+  for (auto *c : b->m)
+    if (c->stage_check > 0)
+      return bfail(b, DG2_EINVAL, "the stage-1 Courant check is not available in batches");
   b->fused = true;
   for (auto *c : b->m) b->fused = b->fused && fused_active(c);
   if (b->fused && b->graph_steps > 1 && (b->graph_steps & 1)) b->graph_steps += 1;

@@ -26,6 +26,10 @@ struct dg2_ctx {
   void *U = nullptr, *U1 = nullptr, *W1 = nullptr, *z = nullptr, *n = nullptr;
   void *U_own = nullptr, *U1_own = nullptr;
   int fused_user = 1;  // dg2_set_step_kernel
+  // stage-1 Courant check (dg2_set_stage_check): repeats allowed per step and
+  // the repeat block (a Ctrl whose step the repeat stage-1 launches read)
+  int stage_check = 0;
+  dg2::Ctrl *ctrl2 = nullptr;
   bool has_ncell = false;
   double n_uniform = 0.0;
   dg2::Ctrl *ctrl = nullptr;
@@ -137,10 +141,10 @@ inline Consts consts(const dg2_ctx *c) {
 }
 
 // Both RK stages in one kernel: DG2-NL in FP32 with the state in library
-// memory.  (In FP64 the fused kernel needs more registers than three
+// memory and no stage-1 Courant check.  (In FP64 the fused kernel needs more registers than three
 // wavefronts per SIMD allow and runs slower than the stage kernels.)
 inline bool fused_active(const dg2_ctx *c) {
-  return c->fused_user && c->f32 && c->cfg.variant == DG2_NL &&
+  return c->fused_user && c->f32 && c->cfg.variant == DG2_NL && c->stage_check == 0 &&
          (c->U == c->U_own || c->U == c->U1_own);
 }
 

@@ -28,7 +28,7 @@ struct Ctrl {
   long long step;      // completed steps
   unsigned long long minbits;  // running min of m_c for the next step (double bits)
   unsigned int flags;  // bit 0: NaN, bit 1: negative mean depth
-  unsigned int pad;
+  unsigned int aux;    // repeat block of the stage-1 Courant check: armed flag
   long long gauge_written;  // samples recorded since the gauge record was reset
   int hyd_k[4];        // per side: hydrograph interval of the last lookup (search hint)
 };

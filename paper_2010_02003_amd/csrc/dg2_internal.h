@@ -65,8 +65,16 @@ hipError_t launch_fused(const Scen<real> &s, const Consts &c, const Launch &L, h
 hipError_t launch_plan(Ctrl *ctrl, const PlanArgs &p, int mode, double t_end, int set_tend,
                        hipStream_t st);
 
+// Courant minimum of s.U into *bits (default: s.ctrl->minbits); skipped when
+// gate is given and its step is idle.
 template <typename real>
-hipError_t launch_cfl(const Scen<real> &s, const Consts &c, hipStream_t st);
+hipError_t launch_cfl(const Scen<real> &s, const Consts &c, hipStream_t st,
+                      const Ctrl *gate = nullptr, unsigned long long *bits = nullptr);
+
+// Stage-1 Courant check after stage 1 (first) or one of its repeats (last:
+// no repeat follows); rep is the repeat block.
+hipError_t launch_stage_check(Ctrl *ctrl, Ctrl *rep, const PlanArgs &p, int first, int last,
+                              hipStream_t st);
 
 template <typename real>
 hipError_t launch_diag(const Scen<real> &s, const Consts &c, double *partials, int nblocks,

@@ -1141,11 +1141,10 @@ __device__ double hydrograph_at(int n, const double *t, const double *Q, double 
   return Q[k] * (1.0 - w) + Q[k + 1] * w;
 }
 
-__device__ void plan_next(Ctrl *c, const PlanArgs &p) {
+// The pending step from time t with size dt: its rain depth and the
+// boundary values (unit inflow or level) at the two stage times.
+__device__ void set_step(Ctrl *c, const PlanArgs &p, double dt) {
   const double t = c->t;
-  const double cand = p.fixed_dt > 0.0 ? p.fixed_dt : fmin(p.cfl * c->cflmin, p.dt_max);
-  double dt = fmin(cand, c->t_end - t);
-  if (!(dt > 0.0)) dt = 0.0;
   c->dt = dt;
   c->rain = p.rain_rate > 0.0 ? p.rain_rate * fmax(0.0, fmin(t + dt, p.rain_te) - fmax(t, p.rain_tb))
                               : 0.0;
@@ -1161,6 +1160,14 @@ __device__ void plan_next(Ctrl *c, const PlanArgs &p) {
       c->qin[sd][1] = 0.0;
     }
   }
+}
+
+__device__ void plan_next(Ctrl *c, const PlanArgs &p) {
+  const double t = c->t;
+  const double cand = p.fixed_dt > 0.0 ? p.fixed_dt : fmin(p.cfl * c->cflmin, p.dt_max);
+  double dt = fmin(cand, c->t_end - t);
+  if (!(dt > 0.0)) dt = 0.0;
+  set_step(c, p, dt);
 }
 
 __device__ void plan_step(Ctrl *c, const PlanArgs &p, int mode, double t_end, int set_tend) {
@@ -1195,6 +1202,34 @@ __global__ void k_plan(Ctrl *c, PlanArgs p, int mode, double t_end, int set_tend
   plan_step(c, p, mode, t_end, set_tend);
 }
 
+// Stage-1 Courant check (an option; one thread).  After stage 1 (first) or a
+// repeat of it, the Courant minimum of the stage-1 result has been gathered
+// in r->minbits.  If the pending step is larger than Cr times that minimum
+// (and a repeat is left), shrink it, plan it anew and arm the repeat block r,
+// whose copy of the step makes the next stage-1 launch on r run; otherwise
+// disarm r, so the remaining repeat launches return at once.  A fixed step
+// size is never changed.
+__global__ void k_stage_check(Ctrl *c, Ctrl *r, PlanArgs p, int first, int last) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (!first && r->aux == 0u) return;
+  const double m1 = __longlong_as_double((long long)r->minbits);
+  r->minbits = kInfBits;
+  const double lim = p.cfl * m1;
+  if (!last && p.fixed_dt <= 0.0 && c->dt > lim) {
+    set_step(c, p, lim);
+    r->dt = c->dt;
+    r->rain = c->rain;
+    for (int sd = 0; sd < 4; ++sd) {
+      r->qin[sd][0] = c->qin[sd][0];
+      r->qin[sd][1] = c->qin[sd][1];
+    }
+    r->aux = 1u;
+  } else {
+    r->dt = 0.0;
+    r->aux = 0u;
+  }
+}
+
 // One thread per scenario of a batch.
 __global__ void k_plan_batch(Ctrl *const *ctrls, const PlanArgs *pa, int n, int mode,
                              double t_end, int set_tend) {
@@ -1203,9 +1238,13 @@ __global__ void k_plan_batch(Ctrl *const *ctrls, const PlanArgs *pa, int n, int 
   plan_step(ctrls[k], pa[k], mode, t_end, set_tend);
 }
 
-// Courant minimum of the current state (after the state was set from the host).
+// Courant minimum of the state s.U, into *bits (after the state was set from
+// the host, or of a stage-1 result for the stage-1 Courant check); returns at
+// once when a gate block is given and its step is idle.
 template <typename real>
-__global__ void __launch_bounds__(256) k_cfl(Scen<real> s, Consts c) {
+__global__ void __launch_bounds__(256) k_cfl(Scen<real> s, Consts c, const Ctrl *gate,
+                                             unsigned long long *bits) {
+  if (gate && !(gate->dt > 0.0)) return;
   const long long n = (long long)s.nx * s.ny;
   const real g = (real)c.g, tol = (real)c.tol;
   double m = __longlong_as_double((long long)kInfBits);
@@ -1214,8 +1253,8 @@ __global__ void __launch_bounds__(256) k_cfl(Scen<real> s, Consts c) {
     const double v = cfl_candidate(s.U[k], s.U[3 * s.P + k], s.U[6 * s.P + k], g, tol, s.dx, s.dy);
     m = v < m ? v : m;
   }
-  const unsigned long long bits = wave_min_u64((unsigned long long)__double_as_longlong(m));
-  if ((threadIdx.x & 63) == 0 && bits != kInfBits) atomicMin(&s.ctrl->minbits, bits);
+  const unsigned long long mb = wave_min_u64((unsigned long long)__double_as_longlong(m));
+  if ((threadIdx.x & 63) == 0 && mb != kInfBits) atomicMin(bits, mb);
 }
 
 // Diagnostics: per-block partial sums (mass, energy, min depth, NaN count),
@@ -1371,11 +1410,19 @@ hipError_t launch_plan(Ctrl *ctrl, const PlanArgs &p, int mode, double t_end, in
 }
 
 template <typename real>
-hipError_t launch_cfl(const Scen<real> &s, const Consts &c, hipStream_t st) {
+hipError_t launch_cfl(const Scen<real> &s, const Consts &c, hipStream_t st, const Ctrl *gate,
+                      unsigned long long *bits) {
   const long long n = (long long)s.nx * s.ny;
   long long blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL((k_cfl<real>), dim3((unsigned)blocks), dim3(256), 0, st, s, c);
+  hipLaunchKernelGGL((k_cfl<real>), dim3((unsigned)blocks), dim3(256), 0, st, s, c, gate,
+                     bits ? bits : &s.ctrl->minbits);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_check(Ctrl *ctrl, Ctrl *rep, const PlanArgs &p, int first, int last,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_stage_check, dim3(1), dim3(64), 0, st, ctrl, rep, p, first, last);
   return hipGetLastError();
 }
 
@@ -1515,8 +1562,10 @@ template hipError_t launch_stage<float>(int, int, const Scen<float> &, const Con
                                         const Launch &, hipStream_t);
 template hipError_t launch_fused<float>(const Scen<float> &, const Consts &, const Launch &,
                                         hipStream_t);
-template hipError_t launch_cfl<double>(const Scen<double> &, const Consts &, hipStream_t);
-template hipError_t launch_cfl<float>(const Scen<float> &, const Consts &, hipStream_t);
+template hipError_t launch_cfl<double>(const Scen<double> &, const Consts &, hipStream_t, const Ctrl *,
+                                       unsigned long long *);
+template hipError_t launch_cfl<float>(const Scen<float> &, const Consts &, hipStream_t, const Ctrl *,
+                                      unsigned long long *);
 template hipError_t launch_diag<double>(const Scen<double> &, const Consts &, double *, int,
                                         double *, hipStream_t);
 template hipError_t launch_diag<float>(const Scen<float> &, const Consts &, double *, int,

@@ -78,6 +78,7 @@ _SIGS = {
                                    POINTER(c_double)]),
     "dg2_set_launch": (c_int32, [c_void_p, c_int32, c_int32]),
     "dg2_set_step_kernel": (c_int32, [c_void_p, c_int32]),
+    "dg2_set_stage_check": (c_int32, [c_void_p, c_int32]),
     "dg2_autotune": (c_int32, [c_void_p, c_double, POINTER(c_int32)]),
     "dg2_state_layout": (c_int32, [c_void_p, POINTER(c_size_t), POINTER(c_size_t)]),
     "dg2_bind_device_state": (c_int32, [c_void_p, c_void_p, c_size_t]),
@@ -252,6 +253,9 @@ class Sim:
 
     def set_step_kernel(self, fused: bool):
         self._check(self._lib.dg2_set_step_kernel(self._ctx, 1 if fused else 0))
+
+    def set_stage_check(self, repeats: int):
+        self._check(self._lib.dg2_set_stage_check(self._ctx, repeats))
 
     def autotune(self, budget_ms: float = 200.0) -> int:
         r = c_int32()
@@ -457,6 +461,8 @@ def sim_from_scenario(sc, stream=None, precision: Optional[str] = None,
         s.set_rainfall(*sc.rain)
     if sc.fixed_dt > 0:
         s.set_fixed_dt(sc.fixed_dt)
+    if sc.stage_check > 0:
+        s.set_stage_check(sc.stage_check)
     s.set_initial_corners(sc.surface, sc.is_eta, sc.qx, sc.qy)
     if sc.gauges is not None:
         s.set_gauges(sc.gauges)

@@ -92,3 +92,24 @@ def test_floodplain_3h_negative_depths_stay_bounded(runs):
     for key, r in runs.items():
         _say("min mean depth after 3 h, %s %s: %.3e m" % (key[0], key[1], r["hmin"]))
     assert runs[("NL", "fp64")]["hmin"] > -0.2 and runs[("LL", "fp64")]["hmin"] > -0.2
+
+
+def test_floodplain_3h_with_stage_check_keeps_depths_positive():
+    """The same 3 h run with the stage-1 Courant check (an option): stage 1
+    is repeated with a smaller step where its own result breaks the Courant
+    bound, and the mean depth stays non-negative throughout."""
+    sc = WL.floodplain()
+    sc.stage_check = 3
+    s = dg2.sim_from_scenario(sc)
+    t0 = time.perf_counter()
+    hmin = 0.0
+    for T in (1800.0, 3600.0, 5400.0, 7200.0, 9000.0, sc.t_end):
+        s.run_to(T)
+        hmin = min(hmin, s.diagnostics()[2])
+    _, t, steps, _ = s.get_state()
+    mass = s.diagnostics()[0]
+    _say("floodplain NL fp64 with stage check: %d steps in %.1f s, volume %.6f m^3, min h0 %.2e m"
+         % (steps, time.perf_counter() - t0, mass, hmin))
+    assert t == sc.t_end
+    assert abs(mass - VOLUME) <= 1e-10 * VOLUME
+    assert hmin >= 0.0

@@ -1,0 +1,94 @@
+"""GPU parity of the stage-1 Courant check (an option, off by default)
+against the oracle's step_checked: on the floodplain's inflow mouth, where
+the plain step drives mean depths negative within 30 steps, the checked run
+matches the oracle step for step (sizes, times, states) over 100 steps and
+keeps every mean depth non-negative over 200; run-to targets are still met
+exactly; a fixed step size turns the check off; batches refuse members that
+use it.  The thin films of this case amplify round-off: the oracle itself,
+with the inflow changed by one part in 1e14, agrees with itself to 7e-16
+after 100 steps but only to 1e-3 after 200, so parity is taken at 100."""
+import numpy as np
+import pytest
+
+from oracle import dg2_oracle as O
+from paper_2010_02003_amd import dg2
+from paper_2010_02003_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _close(gpu, ref, rtol, what):
+    scale = np.maximum(np.abs(ref).reshape(9, -1).max(axis=1), 1.0)
+    err = (np.abs(gpu - ref).reshape(9, -1).max(axis=1) / scale).max()
+    assert np.all(np.isfinite(gpu)) and err <= rtol, "%s: %.3e" % (what, err)
+    return err
+
+
+def test_checked_steps_match_oracle_and_stay_positive():
+    sc = WL.floodplain_mouth(stage_check=3)
+    s = dg2.sim_from_scenario(sc)
+    s.step(100)
+    gpu, t, steps, _ = s.get_state()
+    U, bed, prm = O.setup(sc)
+    r = O.run(U, bed, prm, steps=100)
+    ref = O.to_planes(r.U)
+    e = _close(gpu, ref, 1e-10, "checked run")
+    _say("stage check, mouth 40 x 40, 100 steps: t gpu %.12f oracle %.12f, max rel err %.2e, min h0 %.2e"
+         % (t, r.t, e, gpu[0].min()))
+    assert steps == 100 and abs(t - r.t) <= 1e-12 * r.t
+    assert gpu[0].min() >= 0.0 and ref[0].min() >= 0.0
+    hmin = gpu[0].min()
+    for _ in range(100):
+        s.step(1)
+        hmin = min(hmin, s.diagnostics()[2])
+    assert hmin >= 0.0
+    # the plain step goes negative on the same case
+    p = dg2.sim_from_scenario(WL.floodplain_mouth(stage_check=0))
+    p.step(200)
+    assert p.get_state()[0][0].min() < -1e-3
+
+
+def test_checked_run_to_lands_on_target():
+    sc = WL.floodplain_mouth(stage_check=2)
+    s = dg2.sim_from_scenario(sc)
+    s.run_to(15.0)
+    gpu, t, steps, _ = s.get_state()
+    U, bed, prm = O.setup(sc)
+    r = O.run(U, bed, prm, t_end=15.0)
+    assert t == 15.0 and steps == r.steps and steps < 100
+    _close(gpu, O.to_planes(r.U), 1e-10, "checked run_to")
+
+
+def test_checked_fp32():
+    sc = WL.floodplain_mouth(stage_check=3, precision="fp32")
+    s = dg2.sim_from_scenario(sc)
+    s.step(200)
+    st = s.get_state()[0]
+    ref = dg2.sim_from_scenario(WL.floodplain_mouth(stage_check=3))
+    ref.step(200)
+    r64 = ref.get_state()[0]
+    _say("stage check FP32: min h0 %.2e, max |h0 - FP64| %.2e" % (st[0].min(), np.abs(st[0] - r64[0]).max()))
+    assert st[0].min() >= -1e-6
+    assert np.abs(st[0] - r64[0]).max() < 1e-2
+
+
+def test_fixed_step_turns_the_check_off():
+    sc = WL.floodplain_mouth(stage_check=3)
+    a = dg2.sim_from_scenario(sc)
+    b = dg2.sim_from_scenario(WL.floodplain_mouth(stage_check=0))
+    for s in (a, b):
+        s.set_fixed_dt(0.01)
+        s.step(50)
+    assert np.array_equal(a.get_state()[0], b.get_state()[0])
+
+
+def test_invalid_use():
+    s = dg2.sim_from_scenario(WL.floodplain_mouth(stage_check=1))
+    with pytest.raises(dg2.DG2Error):
+        s.set_stage_check(9)
+    with pytest.raises(dg2.DG2Error):
+        dg2.Batch([s])
