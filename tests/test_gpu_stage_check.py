@@ -28,8 +28,10 @@ def _close(gpu, ref, rtol, what):
     return err
 
 
-def test_checked_steps_match_oracle_and_stay_positive():
+@pytest.mark.parametrize("variant,flux", [("NL", "HLL"), ("LL", "HLL"), ("NL", "ROE")])
+def test_checked_steps_match_oracle_and_stay_positive(variant, flux):
     sc = WL.floodplain_mouth(stage_check=3)
+    sc.variant, sc.flux = variant, flux
     s = dg2.sim_from_scenario(sc)
     s.step(100)
     gpu, t, steps, _ = s.get_state()
@@ -37,8 +39,8 @@ def test_checked_steps_match_oracle_and_stay_positive():
     r = O.run(U, bed, prm, steps=100)
     ref = O.to_planes(r.U)
     e = _close(gpu, ref, 1e-10, "checked run")
-    _say("stage check, mouth 40 x 40, 100 steps: t gpu %.12f oracle %.12f, max rel err %.2e, min h0 %.2e"
-         % (t, r.t, e, gpu[0].min()))
+    _say("stage check %s %s, mouth 40 x 40, 100 steps: t gpu %.12f oracle %.12f, max rel err %.2e, "
+         "min h0 %.2e" % (variant, flux, t, r.t, e, gpu[0].min()))
     assert steps == 100 and abs(t - r.t) <= 1e-12 * r.t
     assert gpu[0].min() >= 0.0 and ref[0].min() >= 0.0
     hmin = gpu[0].min()
@@ -47,7 +49,9 @@ def test_checked_steps_match_oracle_and_stay_positive():
         hmin = min(hmin, s.diagnostics()[2])
     assert hmin >= 0.0
     # the plain step goes negative on the same case
-    p = dg2.sim_from_scenario(WL.floodplain_mouth(stage_check=0))
+    plain = WL.floodplain_mouth(stage_check=0)
+    plain.variant, plain.flux = variant, flux
+    p = dg2.sim_from_scenario(plain)
     p.step(200)
     assert p.get_state()[0][0].min() < -1e-3
 
