@@ -224,16 +224,17 @@ dg2_status dg2_set_launch(dg2_ctx *ctx, int32_t rows_per_wave, int32_t waves_per
  * stage-1 result; while it is larger, stage 1 is repeated (at most n times)
  * with that smaller step, which the time step then takes.  A fixed step size
  * (dg2_set_fixed_dt) is never changed.  Each step queues n repeat launches
- * that return at once when not needed.  The fused step kernel does not run
- * with the check, and batches refuse members that use it.  repeats: 0..8,
- * else DG2_EINVAL. */
+ * that return at once when not needed: repeats of stage 1 with the per-stage
+ * kernels, trials of the whole step with the fused step kernel (whose result
+ * is the same).  Batches refuse members that use it.  repeats: 0..8, else
+ * DG2_EINVAL. */
 dg2_status dg2_set_stage_check(dg2_ctx *ctx, int32_t repeats);
 
 /* How dg2_step runs the two RK stages of Sec. 2.1.2.  fused = 1 (default):
  * one kernel per step that computes stage 1 a row ahead of stage 2 and keeps
  * the stage-1 result in registers, so a step reads and writes the state once;
- * it applies to DG2-NL in FP32 with the state in library memory and no
- * stage-1 Courant check (otherwise the per-stage kernels run).  fused = 0: one kernel per stage, with the stage-1
+ * it applies to DG2-NL in FP32 with the state in library memory (otherwise
+ * the per-stage kernels run).  fused = 0: one kernel per stage, with the stage-1
  * result in a device buffer.  Results are bitwise the same.  DG2_EINVAL for
  * other values. */
 dg2_status dg2_set_step_kernel(dg2_ctx *ctx, int32_t fused);

@@ -141,7 +141,20 @@ hipError_t queue_plan(dg2_ctx *c, int mode, double t_end = 0.0, int set_tend = 0
 hipError_t queue_fused(dg2_ctx *c) {
   Scen<float> s = scen<float>(c);
   s.Uout = (float *)c->U1;
-  const hipError_t e = launch_fused<float>(s, consts(c), fused_launch_of(c), c->stream);
+  hipError_t e;
+  if (c->stage_check > 0) {
+    // trials of the whole step against the staging block; once one is
+    // accepted the remaining trial launches return at once
+    const PlanArgs pa = plan_args(c);
+    s.ctrl = c->ctrl2;
+    e = launch_fused_check(c->ctrl, c->ctrl2, pa, 1, 0, c->stream);
+    for (int k = 0; k <= c->stage_check && e == hipSuccess; ++k) {
+      e = launch_fused<float>(s, consts(c), fused_launch_of(c), c->stream, true);
+      if (e == hipSuccess) e = launch_fused_check(c->ctrl, c->ctrl2, pa, 0, k == c->stage_check, c->stream);
+    }
+  } else {
+    e = launch_fused<float>(s, consts(c), fused_launch_of(c), c->stream);
+  }
   if (e == hipSuccess) std::swap(c->U, c->U1);
   return e;
 }
@@ -312,6 +325,7 @@ dg2_status dg2_create(const dg2_config *cfg, dg2_ctx **out) {
   {
     Ctrl rep{};
     rep.minbits = kInfBits;
+    rep.minbits1 = kInfBits;
     e = hipMemcpy(c->ctrl2, &rep, sizeof(Ctrl), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(hipfail(c, e, "ctrl"));
   }

@@ -141,10 +141,10 @@ inline Consts consts(const dg2_ctx *c) {
 }
 
 // Both RK stages in one kernel: DG2-NL in FP32 with the state in library
-// memory and no stage-1 Courant check.  (In FP64 the fused kernel needs more registers than three
+// memory.  (In FP64 the fused kernel needs more registers than three
 // wavefronts per SIMD allow and runs slower than the stage kernels.)
 inline bool fused_active(const dg2_ctx *c) {
-  return c->fused_user && c->f32 && c->cfg.variant == DG2_NL && c->stage_check == 0 &&
+  return c->fused_user && c->f32 && c->cfg.variant == DG2_NL &&
          (c->U == c->U_own || c->U == c->U1_own);
 }
 

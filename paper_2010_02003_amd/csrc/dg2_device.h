@@ -31,6 +31,8 @@ struct Ctrl {
   unsigned int aux;    // repeat block of the stage-1 Courant check: armed flag
   long long gauge_written;  // samples recorded since the gauge record was reset
   int hyd_k[4];        // per side: hydrograph interval of the last lookup (search hint)
+  unsigned long long minbits1;  // staging block of the stage-1 Courant check: running
+                                // min of m_c over the stage-1 result (double bits)
 };
 
 enum : unsigned { kFlagNaN = 1u, kFlagNegative = 2u };

@@ -60,7 +60,13 @@ hipError_t launch_stage(int stage, int variant, const Scen<real> &s, const Const
 // Both RK stages of a DG2-NL step in one launch (FP32); writes s.Uout,
 // which must not alias s.U.
 template <typename real>
-hipError_t launch_fused(const Scen<real> &s, const Consts &c, const Launch &L, hipStream_t st);
+hipError_t launch_fused(const Scen<real> &s, const Consts &c, const Launch &L, hipStream_t st,
+                        bool check = false);
+
+// Stage-1 Courant check with the fused kernel: begin (copy the pending step
+// into the staging block and arm it) or check a trial (last: accept it).
+hipError_t launch_fused_check(Ctrl *ctrl, Ctrl *rep, const PlanArgs &p, int begin, int last,
+                              hipStream_t st);
 
 hipError_t launch_plan(Ctrl *ctrl, const PlanArgs &p, int mode, double t_end, int set_tend,
                        hipStream_t st);

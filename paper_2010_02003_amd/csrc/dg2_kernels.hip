@@ -585,9 +585,14 @@ __device__ __forceinline__ void ghost_row_y(const Row<real> &r, real tol, Row<re
   row_limits(gh, tol);
 }
 
-template <typename real, int FLUX, bool down>
+// CHECK: a trial of the stage-1 Courant check.  s.ctrl is then the check's
+// staging block: the launch returns at once unless it is armed, and the
+// Courant minimum of the stage-1 result over the output cells goes to its
+// minbits1 (the new state's minimum and flags to its minbits and flags).
+template <typename real, int FLUX, bool down, bool CHECK>
 __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Consts &c, int strip,
                                                 int seg, int R, int lane) {
+  if (CHECK && s.ctrl->aux == 0u) return;
   const double dtd = s.ctrl->dt;
   if (!(dtd > 0.0)) {
     // an idle step (a run-to target was reached): the host swaps the two
@@ -667,6 +672,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
   real zxp = 0, zyp = 0;
 
   double mloc = __longlong_as_double((long long)kInfBits);
+  double m1loc = mloc;
   unsigned flags = 0;
 
   for (int r = afirst; r != astop; r += d) {
@@ -695,6 +701,10 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
 #pragma unroll
       for (int k = 0; k < 9; ++k) u1[k] = curA.W[k] + dt * Lop[k];
       (void)wet_dry_fix(u1, tol);
+      if (CHECK && own && r >= j0 && r < j1) {
+        const double m = cfl_candidate(u1[0], u1[3], u1[6], g, tol, s.dx, s.dy);
+        m1loc = m < m1loc ? m : m1loc;
+      }
     }
     // ghost lanes beyond the grid take U1 of the edge column (mirrored when the row is built)
     if (wedge) {
@@ -806,17 +816,21 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
   }
 
   publish_min(s, lane, mloc, flags);
+  if (CHECK) {
+    const unsigned long long b1 = wave_min_u64((unsigned long long)__double_as_longlong(m1loc));
+    if (lane == 0 && b1 != kInfBits) atomicMin(&s.ctrl->minbits1, b1);
+  }
 }
 
-template <typename real, int FLUX>
+template <typename real, int FLUX, bool CHECK>
 __global__ void __launch_bounds__(256, 3) k_step_nl(Scen<real> s, Consts c, Launch L) {
   int item;
   if (!stage_item<2>(L, item)) return;
   const int strip = item % L.nstrips, seg = item / L.nstrips;
   if (seg & 1)
-    march_fused_dir<real, FLUX, true>(s, c, strip, seg, L.R, threadIdx.x & 63);
+    march_fused_dir<real, FLUX, true, CHECK>(s, c, strip, seg, L.R, threadIdx.x & 63);
   else
-    march_fused_dir<real, FLUX, false>(s, c, strip, seg, L.R, threadIdx.x & 63);
+    march_fused_dir<real, FLUX, false, CHECK>(s, c, strip, seg, L.R, threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------------------
@@ -1117,9 +1131,9 @@ __global__ void __launch_bounds__(256, 3) k_batch_step(const Scen<real> *__restr
     const int seg = __builtin_amdgcn_readfirstlane(items[it].seg);
     const Scen<real> s = scens[sid];
     if (seg & 1)
-      march_fused_dir<real, FLUX, true>(s, c, strip, seg, R, lane);
+      march_fused_dir<real, FLUX, true, false>(s, c, strip, seg, R, lane);
     else
-      march_fused_dir<real, FLUX, false>(s, c, strip, seg, R, lane);
+      march_fused_dir<real, FLUX, false, false>(s, c, strip, seg, R, lane);
   }
 }
 
@@ -1393,13 +1407,73 @@ hipError_t launch_stage(int stage, int variant, const Scen<real> &s, const Const
 }
 
 template <typename real>
-hipError_t launch_fused(const Scen<real> &s, const Consts &c, const Launch &L, hipStream_t st) {
+hipError_t launch_fused(const Scen<real> &s, const Consts &c, const Launch &L, hipStream_t st,
+                        bool check) {
   const dim3 block(64 * L.wpb);
   const dim3 grid((L.nitems + L.wpb - 1) / L.wpb);
-  if (c.flux == kFluxRoe)
-    hipLaunchKernelGGL((k_step_nl<real, kFluxRoe>), grid, block, 0, st, s, c, L);
+  if (c.flux == kFluxRoe) {
+    if (check)
+      hipLaunchKernelGGL((k_step_nl<real, kFluxRoe, true>), grid, block, 0, st, s, c, L);
+    else
+      hipLaunchKernelGGL((k_step_nl<real, kFluxRoe, false>), grid, block, 0, st, s, c, L);
+  } else {
+    if (check)
+      hipLaunchKernelGGL((k_step_nl<real, kFluxHLL, true>), grid, block, 0, st, s, c, L);
+    else
+      hipLaunchKernelGGL((k_step_nl<real, kFluxHLL, false>), grid, block, 0, st, s, c, L);
+  }
+  return hipGetLastError();
+}
+
+// Stage-1 Courant check with the fused step kernel: the step is tried whole
+// (the state at its start stays in place), against the staging block r.
+// k_fused_check_begin copies the pending step into r and arms it; after each
+// trial k_fused_check either shrinks r's step to Cr times the Courant minimum
+// of the trial's stage-1 result (the next trial runs) or accepts the trial:
+// its step size, rain, stage boundary values, the new state's Courant
+// minimum and flags go to the context's block c, and r is disarmed.  Trial
+// k computes stage 1 exactly as the k-th repeat of the per-stage check does,
+// so both paths accept the same step size.
+__global__ void k_fused_check_begin(const Ctrl *c, Ctrl *r) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  *r = *c;
+  r->minbits = kInfBits;
+  r->minbits1 = kInfBits;
+  r->flags = 0u;
+  r->aux = 1u;
+}
+
+__global__ void k_fused_check(Ctrl *c, Ctrl *r, PlanArgs p, int last) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (r->aux == 0u) return;
+  const double m1 = __longlong_as_double((long long)r->minbits1);
+  r->minbits1 = kInfBits;
+  const double lim = p.cfl * m1;
+  if (!last && p.fixed_dt <= 0.0 && r->dt > lim) {
+    set_step(r, p, lim);
+    r->minbits = kInfBits;
+    r->flags = 0u;
+  } else {
+    c->dt = r->dt;
+    c->rain = r->rain;
+    for (int sd = 0; sd < 4; ++sd) {
+      c->qin[sd][0] = r->qin[sd][0];
+      c->qin[sd][1] = r->qin[sd][1];
+      c->hyd_k[sd] = r->hyd_k[sd];
+    }
+    if (r->minbits < c->minbits) c->minbits = r->minbits;
+    c->flags |= r->flags;
+    r->minbits = kInfBits;
+    r->aux = 0u;
+  }
+}
+
+hipError_t launch_fused_check(Ctrl *ctrl, Ctrl *rep, const PlanArgs &p, int begin, int last,
+                              hipStream_t st) {
+  if (begin)
+    hipLaunchKernelGGL(k_fused_check_begin, dim3(1), dim3(64), 0, st, ctrl, rep);
   else
-    hipLaunchKernelGGL((k_step_nl<real, kFluxHLL>), grid, block, 0, st, s, c, L);
+    hipLaunchKernelGGL(k_fused_check, dim3(1), dim3(64), 0, st, ctrl, rep, p, last);
   return hipGetLastError();
 }
 
@@ -1561,7 +1635,7 @@ template hipError_t launch_stage<double>(int, int, const Scen<double> &, const C
 template hipError_t launch_stage<float>(int, int, const Scen<float> &, const Consts &,
                                         const Launch &, hipStream_t);
 template hipError_t launch_fused<float>(const Scen<float> &, const Consts &, const Launch &,
-                                        hipStream_t);
+                                        hipStream_t, bool);
 template hipError_t launch_cfl<double>(const Scen<double> &, const Consts &, hipStream_t, const Ctrl *,
                                        unsigned long long *);
 template hipError_t launch_cfl<float>(const Scen<float> &, const Consts &, hipStream_t, const Ctrl *,

@@ -3,8 +3,9 @@ against the oracle's step_checked: on the floodplain's inflow mouth, where
 the plain step drives mean depths negative within 30 steps, the checked run
 matches the oracle step for step (sizes, times, states) over 100 steps and
 keeps every mean depth non-negative over 200; run-to targets are still met
-exactly; a fixed step size turns the check off; batches refuse members that
-use it.  The thin films of this case amplify round-off: the oracle itself,
+exactly; in FP32 the fused step kernel's trials of the whole step give the
+per-stage kernels' result bit for bit; a fixed step size turns the check off;
+batches refuse members that use it.  The thin films of this case amplify round-off: the oracle itself,
 with the inflow changed by one part in 1e14, agrees with itself to 7e-16
 after 100 steps but only to 1e-3 after 200, so parity is taken at 100."""
 import numpy as np
@@ -78,6 +79,45 @@ def test_checked_fp32():
     _say("stage check FP32: min h0 %.2e, max |h0 - FP64| %.2e" % (st[0].min(), np.abs(st[0] - r64[0]).max()))
     assert st[0].min() >= -1e-6
     assert np.abs(st[0] - r64[0]).max() < 1e-2
+
+
+@pytest.mark.parametrize("flux", ["HLL", "ROE"])
+def test_checked_fused_step_kernel_matches_per_stage_kernels(flux):
+    """With the fused step kernel (the FP32 default) the check tries the
+    whole step; each trial computes stage 1 as the matching repeat of the
+    per-stage check does, so both paths take the same step sizes and give
+    the same states, bit for bit."""
+    sc = WL.floodplain_mouth(stage_check=3, precision="fp32")
+    sc.flux = flux
+    a = dg2.sim_from_scenario(sc)
+    b = dg2.sim_from_scenario(sc)
+    b.set_step_kernel(False)
+    # gauges next to the inflow segment (rows 15..24 of the west side), recorded every step
+    xy = [(sc.x0 + (i + 0.5) * sc.dx, sc.y0 + (j + 0.5) * sc.dy) for i, j in ((0, 19), (3, 20), (8, 17))]
+    for s in (a, b):
+        s.set_gauges(xy, capacity=4096)
+    hmin = 0.0
+    for n in range(4):
+        for s in (a, b):
+            s.step(50)
+        sa, ta, na, da = a.get_state()
+        sb, tb, nb, db = b.get_state()
+        assert na == nb == 50 * (n + 1)
+        assert ta == tb and da == db, (n, ta, tb, da, db)
+        assert np.array_equal(sa, sb), (n, np.abs(sa - sb).max())
+        hmin = min(hmin, float(sa[0].min()))
+    _say("stage check, fused vs per-stage kernels, FP32 %s, 200 steps: t %.9f, min h0 %.2e" % (flux, ta, hmin))
+    assert hmin >= -1e-6
+    # run-to with trials: the target is still met exactly, in the same steps
+    T = float(np.ceil(ta)) + 5.0
+    for s in (a, b):
+        s.run_to(T)
+    sa, ta, na, _ = a.get_state()
+    sb, tb, nb, _ = b.get_state()
+    assert ta == tb == T and na == nb and np.array_equal(sa, sb)
+    ga, tga = a.read_gauges()
+    gb, tgb = b.read_gauges()
+    assert len(tga) == na and np.array_equal(tga, tgb) and np.array_equal(ga, gb)
 
 
 def test_fixed_step_turns_the_check_off():
