@@ -585,11 +585,23 @@ __device__ __forceinline__ void ghost_row_y(const Row<real> &r, real tol, Row<re
   row_limits(gh, tol);
 }
 
+// Whether a fused tile and its halo lie inside the grid: rows j0 - 2 .. j1 + 1
+// and columns i0 - 2 .. i0 + 61 (i0 = 60 strip, j1 = j0 + R).  Such a tile has
+// no boundary face, ghost lane, ghost row or clamped column.
+template <typename real>
+__device__ __forceinline__ bool fused_interior(const Scen<real> &s, int strip, int seg, int R) {
+  const int j0 = seg * R;
+  return strip >= 1 && strip * kStripF + 61 <= s.nx - 1 && j0 >= 2 && j0 + R + 1 <= s.ny - 1;
+}
+
 // CHECK: a trial of the stage-1 Courant check.  s.ctrl is then the check's
 // staging block: the launch returns at once unless it is armed, and the
 // Courant minimum of the stage-1 result over the output cells goes to its
 // minbits1 (the new state's minimum and flags to its minbits and flags).
-template <typename real, int FLUX, bool down, bool CHECK>
+// EDGE = false: an interior tile (fused_interior); the boundary treatment is
+// compiled out, which leaves the march far fewer live scalars and branches
+// (same arithmetic, bitwise equal results).
+template <typename real, int FLUX, bool down, bool CHECK, bool EDGE>
 __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Consts &c, int strip,
                                                 int seg, int R, int lane) {
   if (CHECK && s.ctrl->aux == 0u) return;
@@ -619,12 +631,12 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
   const int afirst = min(max(jfirst - d, 0), ny - 1);
   const int alast = min(max(jlast + d, 0), ny - 1);
   const int astop = alast + d;
-  const bool own = lane >= 2 && lane <= kStripF + 1 && i < s.nx;
-  const int ci = i < 0 ? 0 : (i >= s.nx ? s.nx - 1 : i);
-  const bool mx = (i < 0) || (i >= s.nx);
+  const bool own = lane >= 2 && lane <= kStripF + 1 && (!EDGE || i < s.nx);
+  const int ci = !EDGE ? i : (i < 0 ? 0 : (i >= s.nx ? s.nx - 1 : i));
+  const bool mx = EDGE && ((i < 0) || (i >= s.nx));
   // whether this strip holds the ghost lane west (i = -1) or east (i = nx) of the grid
-  const bool wedge = strip == 0;
-  const bool eedge = s.nx - strip * kStripF + 2 <= 63;
+  const bool wedge = EDGE && strip == 0;
+  const bool eedge = EDGE && s.nx - strip * kStripF + 2 <= 63;
   const real rain = (real)s.ctrl->rain;
   const real gdt = g * dt;
   const real *src = s.U;
@@ -638,11 +650,12 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
   const real qS2 = (real)s.ctrl->qin[2][1], qN2 = (real)s.ctrl->qin[3][1];
   const bool inS = i >= s.seg_first[2] && i <= s.seg_last[2];
   const bool inN = i >= s.seg_first[3] && i <= s.seg_last[3];
-  const bool faceW1 = (i == -1) && side_on(kW, qW1), faceW2 = (i == -1) && side_on(kW, qW2);
-  const bool faceE1 = (i == s.nx - 1) && side_on(kE, qE1);
-  const bool faceE2 = (i == s.nx - 1) && side_on(kE, qE2);
-  const bool colS1 = side_on(kS, qS1) && inS, colS2 = side_on(kS, qS2) && inS;
-  const bool colN1 = side_on(kN, qN1) && inN, colN2 = side_on(kN, qN2) && inN;
+  const bool faceW1 = EDGE && (i == -1) && side_on(kW, qW1);
+  const bool faceW2 = EDGE && (i == -1) && side_on(kW, qW2);
+  const bool faceE1 = EDGE && (i == s.nx - 1) && side_on(kE, qE1);
+  const bool faceE2 = EDGE && (i == s.nx - 1) && side_on(kE, qE2);
+  const bool colS1 = EDGE && side_on(kS, qS1) && inS, colS2 = EDGE && side_on(kS, qS2) && inS;
+  const bool colN1 = EDGE && side_on(kN, qN1) && inN, colN2 = EDGE && side_on(kN, qN2) && inN;
 
   unsigned long long gmask = 0;
   long long gslot = 0;
@@ -731,7 +744,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
       build_row<real, 2>(rb, r, ny, mx, rain, gdt, tol, nxtB);
     }
     if (r == afirst) {
-      if (afirst == jfirst) {
+      if (EDGE && afirst == jfirst) {
         // the row before the first output row is beyond the grid edge
         Row<real> gh;
         ghost_row_y(nxtB, tol, gh);
@@ -786,7 +799,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
     dCA = dFA;
   }
 
-  if (alast == jlast) {
+  if (EDGE && alast == jlast) {
     // the row after the last output row is beyond the grid edge
     Row<real> gh;
     ghost_row_y(curB, tol, gh);
@@ -827,10 +840,18 @@ __global__ void __launch_bounds__(256, 3) k_step_nl(Scen<real> s, Consts c, Laun
   int item;
   if (!stage_item<2>(L, item)) return;
   const int strip = item % L.nstrips, seg = item / L.nstrips;
-  if (seg & 1)
-    march_fused_dir<real, FLUX, true, CHECK>(s, c, strip, seg, L.R, threadIdx.x & 63);
-  else
-    march_fused_dir<real, FLUX, false, CHECK>(s, c, strip, seg, L.R, threadIdx.x & 63);
+  const bool in = fused_interior(s, strip, seg, L.R);
+  if (seg & 1) {
+    if (in)
+      march_fused_dir<real, FLUX, true, CHECK, false>(s, c, strip, seg, L.R, threadIdx.x & 63);
+    else
+      march_fused_dir<real, FLUX, true, CHECK, true>(s, c, strip, seg, L.R, threadIdx.x & 63);
+  } else {
+    if (in)
+      march_fused_dir<real, FLUX, false, CHECK, false>(s, c, strip, seg, L.R, threadIdx.x & 63);
+    else
+      march_fused_dir<real, FLUX, false, CHECK, true>(s, c, strip, seg, L.R, threadIdx.x & 63);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1130,10 +1151,18 @@ __global__ void __launch_bounds__(256, 3) k_batch_step(const Scen<real> *__restr
     const int strip = __builtin_amdgcn_readfirstlane(items[it].strip);
     const int seg = __builtin_amdgcn_readfirstlane(items[it].seg);
     const Scen<real> s = scens[sid];
-    if (seg & 1)
-      march_fused_dir<real, FLUX, true, false>(s, c, strip, seg, R, lane);
-    else
-      march_fused_dir<real, FLUX, false, false>(s, c, strip, seg, R, lane);
+    const bool in = fused_interior(s, strip, seg, R);
+    if (seg & 1) {
+      if (in)
+        march_fused_dir<real, FLUX, true, false, false>(s, c, strip, seg, R, lane);
+      else
+        march_fused_dir<real, FLUX, true, false, true>(s, c, strip, seg, R, lane);
+    } else {
+      if (in)
+        march_fused_dir<real, FLUX, false, false, false>(s, c, strip, seg, R, lane);
+      else
+        march_fused_dir<real, FLUX, false, false, true>(s, c, strip, seg, R, lane);
+    }
   }
 }
 
