@@ -1,6 +1,6 @@
 """Benchmark of the DG2 time step on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload urban|floodplain|dambreak]
+    python bench.py [--steps K] [--warmup W] [--workload urban|urban_fp64|floodplain|dambreak]
 
 Also reported: a batched-ensemble leg (256 uneven FP32 scenarios advanced
 together against the plain solver stepping them one by one) and an adjoint
@@ -85,6 +85,8 @@ def make_workload(name):
 
     if name == "urban":
         return WL.urban()
+    if name == "urban_fp64":
+        return WL.urban(precision="fp64")
     if name == "floodplain":
         return WL.floodplain()
     if name == "dambreak":

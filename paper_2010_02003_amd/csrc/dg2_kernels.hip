@@ -330,7 +330,8 @@ __device__ __forceinline__ void load_own(const Scen<real> &s, long long cidx, Ow
 // rows is always y_face(lower, upper), so the direction changes no result.
 // The carried face (CF, dC) is the south face of the current row when
 // marching up and its north face when marching down.
-template <typename real, int STAGE, int FLUX, bool down>
+// EDGE = false: an interior tile, whose boundary treatment is compiled out.
+template <typename real, int STAGE, int FLUX, bool down, bool EDGE>
 __device__ __forceinline__ void march_nl_dir(const Scen<real> &s, const Consts &c, int strip, int seg,
                                              int R, int lane) {
   const double dtd = s.ctrl->dt;
@@ -342,9 +343,9 @@ __device__ __forceinline__ void march_nl_dir(const Scen<real> &s, const Consts &
   const int j0 = seg * R, j1 = min(j0 + R, s.ny);
   const int d = down ? -1 : 1;
   const int jfirst = down ? j1 - 1 : j0, jstop = down ? j0 - 1 : j1;
-  const bool own = lane >= 1 && lane <= kStripNL && i < s.nx;
-  const int ci = i < 0 ? 0 : (i >= s.nx ? s.nx - 1 : i);
-  const bool mx = (i < 0) || (i >= s.nx);
+  const bool own = lane >= 1 && lane <= kStripNL && (!EDGE || i < s.nx);
+  const int ci = !EDGE ? i : (i < 0 ? 0 : (i >= s.nx ? s.nx - 1 : i));
+  const bool mx = EDGE && ((i < 0) || (i >= s.nx));
   const real rain = (real)s.ctrl->rain;
   const real gdt = g * dt;
   const real *src = STAGE == 1 ? s.U : s.U1;
@@ -354,10 +355,10 @@ __device__ __forceinline__ void march_nl_dir(const Scen<real> &s, const Consts &
   const real qW = (real)s.ctrl->qin[0][si], qE = (real)s.ctrl->qin[1][si];
   const real qS = (real)s.ctrl->qin[2][si], qN = (real)s.ctrl->qin[3][si];
   const int kW = s.bkind[0], kE = s.bkind[1], kS = s.bkind[2], kN = s.bkind[3];
-  const bool faceW = (i == -1) && side_on(kW, qW);
-  const bool faceE = (i == s.nx - 1) && side_on(kE, qE);
-  const bool colS = side_on(kS, qS) && i >= s.seg_first[2] && i <= s.seg_last[2];
-  const bool colN = side_on(kN, qN) && i >= s.seg_first[3] && i <= s.seg_last[3];
+  const bool faceW = EDGE && (i == -1) && side_on(kW, qW);
+  const bool faceE = EDGE && (i == s.nx - 1) && side_on(kE, qE);
+  const bool colS = EDGE && side_on(kS, qS) && i >= s.seg_first[2] && i <= s.seg_last[2];
+  const bool colN = EDGE && side_on(kN, qN) && i >= s.seg_first[3] && i <= s.seg_last[3];
 
   // gauges owned by this wavefront
   unsigned long long gmask = 0;
@@ -472,13 +473,27 @@ __device__ __forceinline__ void march_nl_dir(const Scen<real> &s, const Consts &
   if (STAGE == 2) publish_min(s, lane, mloc, flags);
 }
 
+// Stage 1 of an interior tile (rows j0 - 1 .. j0 + R and columns i0 - 1 ..
+// i0 + 62 inside the grid) runs a march with the boundary treatment compiled
+// out (same arithmetic, bitwise equal): 7 % faster in FP64, 2 % in FP32.
+// Stage 2 keeps one march, whose FP64 form ran 2 % slower split.
 template <typename real, int STAGE, int FLUX>
 __device__ __forceinline__ void march_nl(const Scen<real> &s, const Consts &c, int strip, int seg,
                                          int R, int lane) {
-  if (seg & 1)
-    march_nl_dir<real, STAGE, FLUX, true>(s, c, strip, seg, R, lane);
-  else
-    march_nl_dir<real, STAGE, FLUX, false>(s, c, strip, seg, R, lane);
+  const int j0 = seg * R;
+  const bool in = STAGE == 1 && strip >= 1 && strip * kStripNL + 62 <= s.nx - 1 && j0 >= 1 &&
+                  j0 + R <= s.ny - 1;
+  if (seg & 1) {
+    if (in)
+      march_nl_dir<real, STAGE, FLUX, true, false>(s, c, strip, seg, R, lane);
+    else
+      march_nl_dir<real, STAGE, FLUX, true, true>(s, c, strip, seg, R, lane);
+  } else {
+    if (in)
+      march_nl_dir<real, STAGE, FLUX, false, false>(s, c, strip, seg, R, lane);
+    else
+      march_nl_dir<real, STAGE, FLUX, false, true>(s, c, strip, seg, R, lane);
+  }
 }
 
 // Work item of a wavefront.  Workgroups go to the 8 XCDs round-robin

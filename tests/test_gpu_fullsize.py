@@ -134,6 +134,22 @@ def test_urban_full_size_fp32_windows():
         _say("  window", win, "max rel err %.2e" % e, "wet fraction %.2f" % wet)
 
 
+def test_urban_full_size_fp64_windows():
+    """The urban grid with an FP64 state (the per-stage kernels): the oracle's
+    own precision, so the windows must match to round-off."""
+    sc = WL.urban(precision="fp64")
+    _say("urban 4096 x 4096 FP64: 400 steps, then one step on sampled windows")
+    before, after, t, dt = _run(sc, 400)
+    rng = np.random.default_rng(23)
+    Z = sc.Z
+    jump = np.argwhere(np.abs(np.diff(Z[2000:2200, 2000:2200], axis=0)) > 5.0)
+    j, i = (int(jump[0][0]) + 2000, int(jump[0][1]) + 2000) if len(jump) else (2100, 2100)
+    block = (j - 20, j + 20, i - 20, i + 20)
+    for win in _windows(sc, rng, [block]):
+        e, wet = _check_window(sc, before, after, t, dt, *win, rtol=1e-12, atol=1e-12)
+        _say("  window", win, "max rel err %.2e" % e, "wet fraction %.2f" % wet)
+
+
 def test_ensemble_full_size_batch_equals_plain():
     """The 256-member ensemble as bench.py runs it (autotuned rows, graph
     replay): every member's state after 200 steps equals, bit for bit, the
