@@ -1,6 +1,6 @@
 """Benchmark of the DG2 time step on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload urban|urban_fp64|floodplain|dambreak]
+    python bench.py [--steps K] [--warmup W] [--workload urban|urban_fp64|urban_ll|floodplain|dambreak]
 
 Also reported: a batched-ensemble leg (256 uneven FP32 scenarios advanced
 together against the plain solver stepping them one by one) and an adjoint
@@ -67,6 +67,10 @@ def algorithmic_bytes(sc, esz):
     the Manning plane and writes 9.  A uniform Manning value drops its plane.
     """
     nplane = 1 if isinstance(sc.manning, np.ndarray) else 0
+    if sc.variant == "LL":
+        # DG2-LL: stage 1 also reads z0 and writes the limited stage-1 input
+        # W1 (9 planes); stage 2 reads U1, W1 and the 3 bed planes, no Manning
+        return (9 + 3 + nplane + 18) * esz, (9 + 9 + 3 + 9) * esz
     s1 = (9 + 2 + nplane + 9) * esz
     s2 = (9 + 9 + 2 + nplane + 9) * esz
     return s1, s2
@@ -87,6 +91,8 @@ def make_workload(name):
         return WL.urban()
     if name == "urban_fp64":
         return WL.urban(precision="fp64")
+    if name == "urban_ll":
+        return WL.urban(variant="LL")
     if name == "floodplain":
         return WL.floodplain()
     if name == "dambreak":
@@ -315,7 +321,8 @@ def main():
     traffic = None
     valu_busy = None
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
-    kname = "k_step_nl" if fused else "k_stage_nl"
+    sname = "k_stage_ll" if sc.variant == "LL" else "k_stage_nl"
+    kname = "k_step_nl" if fused else sname
     if os.path.exists(tfile):
         ent = json.load(open(tfile)).get(args.workload)
         if ent and ent.get("kernel_hash") == kernel_source_hash() and ent.get("kernel") == kname:
@@ -354,7 +361,7 @@ def main():
     else:
         ach2 = cells * b2 / (ms2 * 1e-3) / 1e9
         ach1 = cells * b1 / (ms1 * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": "stage 2 (k_stage_nl<%s, 2, HLL>)" % real,
+        roof = {"bound": "hbm", "kernel": "stage 2 (%s<%s, 2, HLL>)" % (sname, real),
                 "achieved": ach2, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach2 / HBM_PEAK_GBS,
                 "traffic": traffic, "bytes_per_cell": b2, "ms_per_launch": ms2,
                 "stage1": {"achieved": ach1, "frac": ach1 / HBM_PEAK_GBS, "bytes_per_cell": b1,

@@ -997,9 +997,11 @@ __device__ __forceinline__ void limited_row(const RowLL<real> &m, const RowLL<re
   row_limits(row, tol);
 }
 
-template <typename real, int STAGE, int FLUX>
-__device__ __forceinline__ void march_ll(const Scen<real> &s, const Consts &c, int strip, int seg,
-                                         int R, int lane) {
+// EDGE = false: an interior tile (rows j0 - 2 .. j0 + R + 1 and columns
+// i0 - 2 .. i0 + 61 inside the grid), whose boundary treatment is compiled out.
+template <typename real, int STAGE, int FLUX, bool EDGE>
+__device__ __forceinline__ void march_ll_tile(const Scen<real> &s, const Consts &c, int strip, int seg,
+                                              int R, int lane) {
   const double dtd = s.ctrl->dt;
   if (!(dtd > 0.0)) return;
 
@@ -1008,9 +1010,9 @@ __device__ __forceinline__ void march_ll(const Scen<real> &s, const Consts &c, i
   const real thx = (real)(c.theta * 0.5 * (double)s.dx), thy = (real)(c.theta * 0.5 * (double)s.dy);
   const int i = strip * kStripLL + lane - 2;
   const int j0 = seg * R, j1 = min(j0 + R, s.ny);
-  const bool own = lane >= 2 && lane < 2 + kStripLL && i < s.nx;
-  bool mx;
-  const int ci = reflect2(i, s.nx, mx);
+  const bool own = lane >= 2 && lane < 2 + kStripLL && (!EDGE || i < s.nx);
+  bool mx = false;
+  const int ci = EDGE ? reflect2(i, s.nx, mx) : i;
   const real rain = (real)s.ctrl->rain;
   const real gdt = g * dt;
   const real *src = STAGE == 1 ? s.U : s.U1;
@@ -1020,10 +1022,10 @@ __device__ __forceinline__ void march_ll(const Scen<real> &s, const Consts &c, i
   const real qW = (real)s.ctrl->qin[0][si], qE = (real)s.ctrl->qin[1][si];
   const real qS = (real)s.ctrl->qin[2][si], qN = (real)s.ctrl->qin[3][si];
   const int kW = s.bkind[0], kE = s.bkind[1], kS = s.bkind[2], kN = s.bkind[3];
-  const bool faceW = (i == -1) && side_on(kW, qW);
-  const bool faceE = (i == s.nx - 1) && side_on(kE, qE);
-  const bool colS = side_on(kS, qS) && i >= s.seg_first[2] && i <= s.seg_last[2];
-  const bool colN = side_on(kN, qN) && i >= s.seg_first[3] && i <= s.seg_last[3];
+  const bool faceW = EDGE && (i == -1) && side_on(kW, qW);
+  const bool faceE = EDGE && (i == s.nx - 1) && side_on(kE, qE);
+  const bool colS = EDGE && side_on(kS, qS) && i >= s.seg_first[2] && i <= s.seg_last[2];
+  const bool colN = EDGE && side_on(kN, qN) && i >= s.seg_first[3] && i <= s.seg_last[3];
 
   unsigned long long gmask = 0;
   long long gslot = 0;
@@ -1108,6 +1110,18 @@ __device__ __forceinline__ void march_ll(const Scen<real> &s, const Consts &c, i
   }
 
   if (STAGE == 2) publish_min(s, lane, mloc, flags);
+}
+
+template <typename real, int STAGE, int FLUX>
+__device__ __forceinline__ void march_ll(const Scen<real> &s, const Consts &c, int strip, int seg,
+                                         int R, int lane) {
+  const int j0 = seg * R;
+  const bool in = strip >= 1 && strip * kStripLL + 61 <= s.nx - 1 && j0 >= 2 &&
+                  j0 + R + 1 <= s.ny - 1;
+  if (in)
+    march_ll_tile<real, STAGE, FLUX, false>(s, c, strip, seg, R, lane);
+  else
+    march_ll_tile<real, STAGE, FLUX, true>(s, c, strip, seg, R, lane);
 }
 
 template <typename real, int STAGE, int FLUX>
