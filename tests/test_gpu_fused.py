@@ -59,7 +59,9 @@ def _random_sim(nx, ny, prec, flux, seed, bcs=True):
     return make
 
 
-SIZES = [(70, 45), (1, 5), (6, 1), (60, 7), (61, 3), (120, 9), (121, 130), (59, 61), (2, 2)]
+# (250, 140) has interior tiles (halo inside the grid) in both the fused and
+# the per-stage kernels, next to edge tiles with every boundary kind
+SIZES = [(70, 45), (1, 5), (6, 1), (60, 7), (61, 3), (120, 9), (121, 130), (59, 61), (2, 2), (250, 140)]
 
 
 @pytest.mark.parametrize("nx,ny", SIZES)

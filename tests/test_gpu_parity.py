@@ -216,7 +216,9 @@ def test_from_dry_channel_filling_matches_oracle():
     _assert_close(gpu, O.to_planes(r.U), 1e-10, "channel filling")
 
 
-@pytest.mark.parametrize("nx,ny,theta", [(70, 45, 1.0), (131, 9, 0.0), (2, 6, 0.5), (61, 61, 10.0)])
+# (130, 40) has interior tiles (halo inside the grid) next to edge tiles
+@pytest.mark.parametrize("nx,ny,theta", [(70, 45, 1.0), (131, 9, 0.0), (2, 6, 0.5), (61, 61, 10.0),
+                                         (130, 40, 1.0)])
 def test_ll_one_step_random_state(nx, ny, theta):
     """DG2-LL: shock detector (Eq. 6) and minmod (Eq. 7) on random wet/dry modes."""
     _say("DG2-LL one step", nx, ny, "theta", theta)
