@@ -540,6 +540,25 @@ def test_energy_of_lake_at_rest_is_closed_form():
     assert abs(O.energy(U, bed, prm) - 0.5 * G * 2.25 * nx * ny * dx * dx) < 1e-10
 
 
+def test_energy_of_uniform_stream_on_a_sloping_bed_is_closed_form():
+    """Eq. (12) with every term at work: kinetic energy h |u|^2 / 2, g h^2 / 2
+    and the bed term g h z, for a uniform depth and discharge over a planar
+    bed (the 2 x 2 Gauss rule is exact for these polynomials)."""
+    nx, ny, dx, dy = 6, 3, 2.0, 1.5
+    h, qx, qy = 1.2, 0.6, -0.3
+    xs = np.arange(nx + 1) * dx
+    ys = np.arange(ny + 1) * dy
+    X, Y = np.meshgrid(xs, ys)
+    Z = 0.1 * X + 0.05 * Y
+    U = O.initial_state(Z, np.full_like(Z, h), False, np.full_like(Z, qx), np.full_like(Z, qy))
+    bed = O.bed_from_corners(Z)
+    prm = _prm(nx, ny, dx, dy)
+    area = nx * dx * ny * dy
+    z_mean = 0.1 * nx * dx / 2 + 0.05 * ny * dy / 2
+    exact = area * (0.5 * (qx * qx + qy * qy) / h + 0.5 * G * h * h + G * h * z_mean)
+    assert abs(O.energy(U, bed, prm) - exact) < 1e-10 * exact
+
+
 def test_paper_constants_fixture():
     c = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
     prm = O.Params(nx=1, ny=1, dx=1.0, dy=1.0)
