@@ -600,6 +600,18 @@ __device__ __forceinline__ void ghost_row_y(const Row<real> &r, real tol, Row<re
   row_limits(gh, tol);
 }
 
+// Values one row of the fused march hands to the next.
+template <typename real>
+struct FusedCarry {
+  Row<real> A;       // stage-1 input of the current row
+  Raw<real, 1> raw;  // raw planes of the row after it
+  real CA[4];        // stage-1 face behind the current row (3 fluxes, bed-step term)
+  Row<real> B;       // U1 of the row behind (stage 2 outputs it next)
+  real CB[4];        // stage-2 face behind that row
+  real W1[9];        // stage-1 input of the row behind
+  real zx, zy;       // bed slopes of the row behind
+};
+
 // Whether a fused tile and its halo lie inside the grid: rows j0 - 2 .. j1 + 1
 // and columns i0 - 2 .. i0 + 61 (i0 = 60 strip, j1 = j0 + R).  Such a tile has
 // no boundary face, ghost lane, ghost row or clamped column.
@@ -679,168 +691,294 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
     gslot = (s.ctrl->gauge_written % s.g_cap) * s.ng;
   }
 
-  // stage 1 march state: current row, raw planes of the next two rows, face behind
-  Row<real> curA;
-  Raw<real, 1> rawA, rawN;
-  real CA0, CA1, CA2, dCA;
-  {
-    Row<real> back;
-    load_raw<real, 1>(s, src, afirst - d, ci, rawA);
-    load_raw<real, 1>(s, src, afirst, ci, rawN);
-    build_row<real, 1>(rawA, afirst - d, ny, mx, rain, gdt, tol, back);
-    load_raw<real, 1>(s, src, afirst + d, ci, rawA);
-    build_row<real, 1>(rawN, afirst, ny, mx, rain, gdt, tol, curA);
-    face_behind<FLUX, down>(s, afirst, i, back, curA, colS1, colN1, qS1, qN1, g, tol, CA0, CA1, CA2,
-                            dCA);
-  }
-  // stage 2 state: U1 row behind, the face behind it, and its stage-1 input and bed slopes
-  Row<real> curB;
-  real CB0 = 0, CB1 = 0, CB2 = 0, dCB = 0;
-  real W1p[9];
-  real zxp = 0, zyp = 0;
-
   double mloc = __longlong_as_double((long long)kInfBits);
   double m1loc = mloc;
   unsigned flags = 0;
-
-  for (int r = afirst; r != astop; r += d) {
-    if (down ? (r - 2 >= alast - 1) : (r + 2 <= alast + 1))
-      load_raw<real, 1>(s, src, r + 2 * d, ci, rawN);
-    const unsigned offA = (unsigned)(r * s.nx + ci) * (unsigned)sizeof(real);
-    const real zx = ld_at(s.z + s.P, offA), zy = ld_at(s.z + 2 * s.P, offA);
-
-    // ---- stage 1 on row r ----
-    Row<real> nxtA;
-    build_row<real, 1>(rawA, r + d, ny, mx, rain, gdt, tol, nxtA);
-    real FA0, FA1, FA2, dFA;
-    face_ahead<FLUX, down>(s, r, i, curA, nxtA, colS1, colN1, qS1, qN1, g, tol, FA0, FA1, FA2, dFA);
-    real u1[9];
+  if constexpr (!EDGE) {
+    // Interior tiles: the row loop written out twice per iteration, with the
+    // values carried from row to row in two slots that swap roles, so no
+    // register is copied between rows.
+    FusedCarry<real> K[2];
     {
-      real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
-      fused_x_faces<FLUX>(s, r, curA, faceW1, faceE1, qW1, qE1, g, tol, FE0, FE1, FE2, FW0, FW1, FW2,
-                          dE, dW);
-      const real GN0 = down ? CA0 : FA0, GN1 = down ? CA1 : FA1, GN2 = down ? CA2 : FA2;
-      const real GS0 = down ? FA0 : CA0, GS1 = down ? FA1 : CA1, GS2 = down ? FA2 : CA2;
-      const real dN = down ? dCA : dFA, dS = down ? dFA : dCA;
-      real Lop[9];
-      cell_operator(curA, FE0, FE1, FE2, FW0, FW1, FW2, GN0, GN1, GN2, GS0, GS1, GS2,
-                    zx - half * dE + half * dW, zy - half * dN + half * dS, g, tol, s.idx, s.idy,
-                    Lop);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) u1[k] = curA.W[k] + dt * Lop[k];
-      (void)wet_dry_fix(u1, tol);
-      if (CHECK && own && r >= j0 && r < j1) {
-        const double m = cfl_candidate(u1[0], u1[3], u1[6], g, tol, s.dx, s.dy);
-        m1loc = m < m1loc ? m : m1loc;
-      }
+      Row<real> back;
+      load_raw<real, 1>(s, src, afirst - d, ci, K[0].raw);
+      load_raw<real, 1>(s, src, afirst, ci, K[1].raw);
+      build_row<real, 1>(K[0].raw, afirst - d, ny, mx, rain, gdt, tol, back);
+      load_raw<real, 1>(s, src, afirst + d, ci, K[0].raw);
+      build_row<real, 1>(K[1].raw, afirst, ny, mx, rain, gdt, tol, K[0].A);
+      face_behind<FLUX, down>(s, afirst, i, back, K[0].A, colS1, colN1, qS1, qN1, g, tol, K[0].CA[0],
+                              K[0].CA[1], K[0].CA[2], K[0].CA[3]);
     }
-    // ghost lanes beyond the grid take U1 of the edge column (mirrored when the row is built)
-    if (wedge) {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        const real v = __shfl_down(u1[k], 1, 64);
-        if (i == -1) u1[k] = v;
-      }
-    }
-    if (eedge) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        const real v = __shfl_up(u1[k], 1, 64);
-        if (i == s.nx) u1[k] = v;
-      }
-    }
+    for (int k = 0; k < 4; ++k) K[0].CB[k] = 0;
+    K[0].zx = 0;
+    K[0].zy = 0;
+    auto row = [&](int r, FusedCarry<real> &kc, FusedCarry<real> &kn) __attribute__((always_inline)) {
+      if (down ? (r - 2 >= alast - 1) : (r + 2 <= alast + 1))
+        load_raw<real, 1>(s, src, r + 2 * d, ci, kn.raw);
+      const unsigned offA = (unsigned)(r * s.nx + ci) * (unsigned)sizeof(real);
+      const real zx = ld_at(s.z + s.P, offA), zy = ld_at(s.z + 2 * s.P, offA);
 
-    // ---- stage 2: U1 of row r arrives ----
-    Row<real> nxtB;
-    {
-      Raw<real, 2> rb;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) rb.W[k] = u1[k];
-      build_row<real, 2>(rb, r, ny, mx, rain, gdt, tol, nxtB);
-    }
-    if (r == afirst) {
-      if (EDGE && afirst == jfirst) {
-        // the row before the first output row is beyond the grid edge
-        Row<real> gh;
-        ghost_row_y(nxtB, tol, gh);
-        face_behind<FLUX, down>(s, r, i, gh, nxtB, colS2, colN2, qS2, qN2, g, tol, CB0, CB1, CB2,
-                                dCB);
-      }
-    } else {
-      const int kB = r - d;
-      real FB0, FB1, FB2, dFB;
-      face_ahead<FLUX, down>(s, kB, i, curB, nxtB, colS2, colN2, qS2, qN2, g, tol, FB0, FB1, FB2,
-                             dFB);
-      if (kB >= j0 && kB < j1) {
-        // output row kB
+      // ---- stage 1 on row r ----
+      build_row<real, 1>(kc.raw, r + d, ny, mx, rain, gdt, tol, kn.A);
+      face_ahead<FLUX, down>(s, r, i, kc.A, kn.A, colS1, colN1, qS1, qN1, g, tol, kn.CA[0], kn.CA[1],
+                             kn.CA[2], kn.CA[3]);
+      real u1[9];
+      {
         real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
-        fused_x_faces<FLUX>(s, kB, curB, faceW2, faceE2, qW2, qE2, g, tol, FE0, FE1, FE2, FW0, FW1,
-                            FW2, dE, dW);
-        if (own) {
-          const real GN0 = down ? CB0 : FB0, GN1 = down ? CB1 : FB1, GN2 = down ? CB2 : FB2;
-          const real GS0 = down ? FB0 : CB0, GS1 = down ? FB1 : CB1, GS2 = down ? FB2 : CB2;
-          const real dN = down ? dCB : dFB, dS = down ? dFB : dCB;
-          real Lop[9];
-          cell_operator(curB, FE0, FE1, FE2, FW0, FW1, FW2, GN0, GN1, GN2, GS0, GS1, GS2,
-                        zxp - half * dE + half * dW, zyp - half * dN + half * dS, g, tol, s.idx,
-                        s.idy, Lop);
-          real o[9];
+        fused_x_faces<FLUX>(s, r, kc.A, faceW1, faceE1, qW1, qE1, g, tol, FE0, FE1, FE2, FW0, FW1, FW2,
+                            dE, dW);
+        const real *CN = down ? kc.CA : kn.CA, *CS = down ? kn.CA : kc.CA;
+        const real GN0 = CN[0], GN1 = CN[1], GN2 = CN[2];
+        const real GS0 = CS[0], GS1 = CS[1], GS2 = CS[2];
+        const real dN = down ? kc.CA[3] : kn.CA[3], dS = down ? kn.CA[3] : kc.CA[3];
+        real Lop[9];
+        cell_operator(kc.A, FE0, FE1, FE2, FW0, FW1, FW2, GN0, GN1, GN2, GS0, GS1, GS2,
+                      zx - half * dE + half * dW, zy - half * dN + half * dS, g, tol, s.idx, s.idy,
+                      Lop);
 #pragma unroll
-          for (int k = 0; k < 9; ++k) o[k] = half * (W1p[k] + curB.W[k] + dt * Lop[k]);
-          (void)wet_dry_fix(o, tol);
-          const long long cidx = (long long)kB * s.nx + i;
-          const unsigned off = (unsigned)cidx * (unsigned)sizeof(real);
-#pragma unroll
-          for (int k = 0; k < 9; ++k) st_at(dst + k * s.P, off, o[k]);
-          new_state_checks(s, o, cidx, gmask, gslot, g, tol, mloc, flags);
+        for (int k = 0; k < 9; ++k) u1[k] = kc.A.W[k] + dt * Lop[k];
+        (void)wet_dry_fix(u1, tol);
+        if (CHECK && own && r >= j0 && r < j1) {
+          const double m = cfl_candidate(u1[0], u1[3], u1[6], g, tol, s.dx, s.dy);
+          m1loc = m < m1loc ? m : m1loc;
         }
       }
-      CB0 = FB0;
-      CB1 = FB1;
-      CB2 = FB2;
-      dCB = dFB;
-    }
-    curB = nxtB;
+      // ghost lanes beyond the grid take U1 of the edge column (mirrored when the row is built)
+      if (wedge) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) W1p[k] = curA.W[k];
-    zxp = zx;
-    zyp = zy;
+        for (int k = 0; k < 9; ++k) {
+          const real v = __shfl_down(u1[k], 1, 64);
+          if (i == -1) u1[k] = v;
+        }
+      }
+      if (eedge) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          const real v = __shfl_up(u1[k], 1, 64);
+          if (i == s.nx) u1[k] = v;
+        }
+      }
 
-    curA = nxtA;
-    rawA = rawN;
-    CA0 = FA0;
-    CA1 = FA1;
-    CA2 = FA2;
-    dCA = dFA;
-  }
-
-  if (EDGE && alast == jlast) {
-    // the row after the last output row is beyond the grid edge
-    Row<real> gh;
-    ghost_row_y(curB, tol, gh);
-    real FB0, FB1, FB2, dFB;
-    face_ahead<FLUX, down>(s, jlast, i, curB, gh, colS2, colN2, qS2, qN2, g, tol, FB0, FB1, FB2, dFB);
-    real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
-    fused_x_faces<FLUX>(s, jlast, curB, faceW2, faceE2, qW2, qE2, g, tol, FE0, FE1, FE2, FW0, FW1,
-                        FW2, dE, dW);
-    if (own) {
-      const real GN0 = down ? CB0 : FB0, GN1 = down ? CB1 : FB1, GN2 = down ? CB2 : FB2;
-      const real GS0 = down ? FB0 : CB0, GS1 = down ? FB1 : CB1, GS2 = down ? FB2 : CB2;
-      const real dN = down ? dCB : dFB, dS = down ? dFB : dCB;
-      real Lop[9];
-      cell_operator(curB, FE0, FE1, FE2, FW0, FW1, FW2, GN0, GN1, GN2, GS0, GS1, GS2,
-                    zxp - half * dE + half * dW, zyp - half * dN + half * dS, g, tol, s.idx, s.idy,
-                    Lop);
-      real o[9];
+      // ---- stage 2: U1 of row r arrives ----
+      {
+        Raw<real, 2> rb;
 #pragma unroll
-      for (int k = 0; k < 9; ++k) o[k] = half * (W1p[k] + curB.W[k] + dt * Lop[k]);
-      (void)wet_dry_fix(o, tol);
-      const long long cidx = (long long)jlast * s.nx + i;
-      const unsigned off = (unsigned)cidx * (unsigned)sizeof(real);
+        for (int k = 0; k < 9; ++k) rb.W[k] = u1[k];
+        build_row<real, 2>(rb, r, ny, mx, rain, gdt, tol, kn.B);
+      }
+      if (r == afirst) {
+        if (EDGE && afirst == jfirst) {
+          // the row before the first output row is beyond the grid edge
+          Row<real> gh;
+          ghost_row_y(kn.B, tol, gh);
+          face_behind<FLUX, down>(s, r, i, gh, kn.B, colS2, colN2, qS2, qN2, g, tol, kn.CB[0], kn.CB[1],
+                                  kn.CB[2], kn.CB[3]);
+        }
+      } else {
+        const int kB = r - d;
+        face_ahead<FLUX, down>(s, kB, i, kc.B, kn.B, colS2, colN2, qS2, qN2, g, tol, kn.CB[0], kn.CB[1],
+                               kn.CB[2], kn.CB[3]);
+        if (kB >= j0 && kB < j1) {
+          // output row kB
+          real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
+          fused_x_faces<FLUX>(s, kB, kc.B, faceW2, faceE2, qW2, qE2, g, tol, FE0, FE1, FE2, FW0, FW1,
+                              FW2, dE, dW);
+          if (own) {
+            const real *CN = down ? kc.CB : kn.CB, *CS = down ? kn.CB : kc.CB;
+            const real GN0 = CN[0], GN1 = CN[1], GN2 = CN[2];
+            const real GS0 = CS[0], GS1 = CS[1], GS2 = CS[2];
+            const real dN = down ? kc.CB[3] : kn.CB[3], dS = down ? kn.CB[3] : kc.CB[3];
+            real Lop[9];
+            cell_operator(kc.B, FE0, FE1, FE2, FW0, FW1, FW2, GN0, GN1, GN2, GS0, GS1, GS2,
+                          kc.zx - half * dE + half * dW, kc.zy - half * dN + half * dS, g, tol, s.idx,
+                          s.idy, Lop);
+            real o[9];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) st_at(dst + k * s.P, off, o[k]);
-      new_state_checks(s, o, cidx, gmask, gslot, g, tol, mloc, flags);
+            for (int k = 0; k < 9; ++k) o[k] = half * (kc.W1[k] + kc.B.W[k] + dt * Lop[k]);
+            (void)wet_dry_fix(o, tol);
+            const long long cidx = (long long)kB * s.nx + i;
+            const unsigned off = (unsigned)cidx * (unsigned)sizeof(real);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) st_at(dst + k * s.P, off, o[k]);
+            new_state_checks(s, o, cidx, gmask, gslot, g, tol, mloc, flags);
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) kn.W1[k] = kc.A.W[k];
+      kn.zx = zx;
+      kn.zy = zy;
+      };
+    int r = afirst;
+    int left = (astop - afirst) * d;
+    for (; left >= 2; left -= 2, r += 2 * d) {
+      row(r, K[0], K[1]);
+      row(r + d, K[1], K[0]);
     }
+    if (left == 1) row(r, K[0], K[1]);
+  } else {
+    // stage 1 march state: current row, raw planes of the next two rows, face behind
+    Row<real> curA;
+    Raw<real, 1> rawA, rawN;
+    real CA0, CA1, CA2, dCA;
+    {
+      Row<real> back;
+      load_raw<real, 1>(s, src, afirst - d, ci, rawA);
+      load_raw<real, 1>(s, src, afirst, ci, rawN);
+      build_row<real, 1>(rawA, afirst - d, ny, mx, rain, gdt, tol, back);
+      load_raw<real, 1>(s, src, afirst + d, ci, rawA);
+      build_row<real, 1>(rawN, afirst, ny, mx, rain, gdt, tol, curA);
+      face_behind<FLUX, down>(s, afirst, i, back, curA, colS1, colN1, qS1, qN1, g, tol, CA0, CA1, CA2,
+                              dCA);
+    }
+    // stage 2 state: U1 row behind, the face behind it, and its stage-1 input and bed slopes
+    Row<real> curB;
+    real CB0 = 0, CB1 = 0, CB2 = 0, dCB = 0;
+    real W1p[9];
+    real zxp = 0, zyp = 0;
+
+
+    for (int r = afirst; r != astop; r += d) {
+      if (down ? (r - 2 >= alast - 1) : (r + 2 <= alast + 1))
+        load_raw<real, 1>(s, src, r + 2 * d, ci, rawN);
+      const unsigned offA = (unsigned)(r * s.nx + ci) * (unsigned)sizeof(real);
+      const real zx = ld_at(s.z + s.P, offA), zy = ld_at(s.z + 2 * s.P, offA);
+
+      // ---- stage 1 on row r ----
+      Row<real> nxtA;
+      build_row<real, 1>(rawA, r + d, ny, mx, rain, gdt, tol, nxtA);
+      real FA0, FA1, FA2, dFA;
+      face_ahead<FLUX, down>(s, r, i, curA, nxtA, colS1, colN1, qS1, qN1, g, tol, FA0, FA1, FA2, dFA);
+      real u1[9];
+      {
+        real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
+        fused_x_faces<FLUX>(s, r, curA, faceW1, faceE1, qW1, qE1, g, tol, FE0, FE1, FE2, FW0, FW1, FW2,
+                            dE, dW);
+        const real GN0 = down ? CA0 : FA0, GN1 = down ? CA1 : FA1, GN2 = down ? CA2 : FA2;
+        const real GS0 = down ? FA0 : CA0, GS1 = down ? FA1 : CA1, GS2 = down ? FA2 : CA2;
+        const real dN = down ? dCA : dFA, dS = down ? dFA : dCA;
+        real Lop[9];
+        cell_operator(curA, FE0, FE1, FE2, FW0, FW1, FW2, GN0, GN1, GN2, GS0, GS1, GS2,
+                      zx - half * dE + half * dW, zy - half * dN + half * dS, g, tol, s.idx, s.idy,
+                      Lop);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) u1[k] = curA.W[k] + dt * Lop[k];
+        (void)wet_dry_fix(u1, tol);
+        if (CHECK && own && r >= j0 && r < j1) {
+          const double m = cfl_candidate(u1[0], u1[3], u1[6], g, tol, s.dx, s.dy);
+          m1loc = m < m1loc ? m : m1loc;
+        }
+      }
+      // ghost lanes beyond the grid take U1 of the edge column (mirrored when the row is built)
+      if (wedge) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          const real v = __shfl_down(u1[k], 1, 64);
+          if (i == -1) u1[k] = v;
+        }
+      }
+      if (eedge) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          const real v = __shfl_up(u1[k], 1, 64);
+          if (i == s.nx) u1[k] = v;
+        }
+      }
+
+      // ---- stage 2: U1 of row r arrives ----
+      Row<real> nxtB;
+      {
+        Raw<real, 2> rb;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) rb.W[k] = u1[k];
+        build_row<real, 2>(rb, r, ny, mx, rain, gdt, tol, nxtB);
+      }
+      if (r == afirst) {
+        if (EDGE && afirst == jfirst) {
+          // the row before the first output row is beyond the grid edge
+          Row<real> gh;
+          ghost_row_y(nxtB, tol, gh);
+          face_behind<FLUX, down>(s, r, i, gh, nxtB, colS2, colN2, qS2, qN2, g, tol, CB0, CB1, CB2,
+                                  dCB);
+        }
+      } else {
+        const int kB = r - d;
+        real FB0, FB1, FB2, dFB;
+        face_ahead<FLUX, down>(s, kB, i, curB, nxtB, colS2, colN2, qS2, qN2, g, tol, FB0, FB1, FB2,
+                               dFB);
+        if (kB >= j0 && kB < j1) {
+          // output row kB
+          real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
+          fused_x_faces<FLUX>(s, kB, curB, faceW2, faceE2, qW2, qE2, g, tol, FE0, FE1, FE2, FW0, FW1,
+                              FW2, dE, dW);
+          if (own) {
+            const real GN0 = down ? CB0 : FB0, GN1 = down ? CB1 : FB1, GN2 = down ? CB2 : FB2;
+            const real GS0 = down ? FB0 : CB0, GS1 = down ? FB1 : CB1, GS2 = down ? FB2 : CB2;
+            const real dN = down ? dCB : dFB, dS = down ? dFB : dCB;
+            real Lop[9];
+            cell_operator(curB, FE0, FE1, FE2, FW0, FW1, FW2, GN0, GN1, GN2, GS0, GS1, GS2,
+                          zxp - half * dE + half * dW, zyp - half * dN + half * dS, g, tol, s.idx,
+                          s.idy, Lop);
+            real o[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) o[k] = half * (W1p[k] + curB.W[k] + dt * Lop[k]);
+            (void)wet_dry_fix(o, tol);
+            const long long cidx = (long long)kB * s.nx + i;
+            const unsigned off = (unsigned)cidx * (unsigned)sizeof(real);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) st_at(dst + k * s.P, off, o[k]);
+            new_state_checks(s, o, cidx, gmask, gslot, g, tol, mloc, flags);
+          }
+        }
+        CB0 = FB0;
+        CB1 = FB1;
+        CB2 = FB2;
+        dCB = dFB;
+      }
+      curB = nxtB;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) W1p[k] = curA.W[k];
+      zxp = zx;
+      zyp = zy;
+
+      curA = nxtA;
+      rawA = rawN;
+      CA0 = FA0;
+      CA1 = FA1;
+      CA2 = FA2;
+      dCA = dFA;
+    }
+
+    if (EDGE && alast == jlast) {
+      // the row after the last output row is beyond the grid edge
+      Row<real> gh;
+      ghost_row_y(curB, tol, gh);
+      real FB0, FB1, FB2, dFB;
+      face_ahead<FLUX, down>(s, jlast, i, curB, gh, colS2, colN2, qS2, qN2, g, tol, FB0, FB1, FB2, dFB);
+      real FE0, FE1, FE2, FW0, FW1, FW2, dE, dW;
+      fused_x_faces<FLUX>(s, jlast, curB, faceW2, faceE2, qW2, qE2, g, tol, FE0, FE1, FE2, FW0, FW1,
+                          FW2, dE, dW);
+      if (own) {
+        const real GN0 = down ? CB0 : FB0, GN1 = down ? CB1 : FB1, GN2 = down ? CB2 : FB2;
+        const real GS0 = down ? FB0 : CB0, GS1 = down ? FB1 : CB1, GS2 = down ? FB2 : CB2;
+        const real dN = down ? dCB : dFB, dS = down ? dFB : dCB;
+        real Lop[9];
+        cell_operator(curB, FE0, FE1, FE2, FW0, FW1, FW2, GN0, GN1, GN2, GS0, GS1, GS2,
+                      zxp - half * dE + half * dW, zyp - half * dN + half * dS, g, tol, s.idx, s.idy,
+                      Lop);
+        real o[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) o[k] = half * (W1p[k] + curB.W[k] + dt * Lop[k]);
+        (void)wet_dry_fix(o, tol);
+        const long long cidx = (long long)jlast * s.nx + i;
+        const unsigned off = (unsigned)cidx * (unsigned)sizeof(real);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) st_at(dst + k * s.P, off, o[k]);
+        new_state_checks(s, o, cidx, gmask, gslot, g, tol, mloc, flags);
+      }
+    }
+
   }
 
   publish_min(s, lane, mloc, flags);
