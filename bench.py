@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DG2 element-stage updates/s + % HBM peak; batched & adjoint vs plain"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+VALU_ISSUE_PEAK_G = 256 * 4 * 2.4 / 4  # wave64 VALU instructions per ns: CUs x SIMDs x GHz / cycles
 
 # Table 3 of the paper (Sec. 3.3): wall-clock seconds of DG2-NL and DG2-LL on
 # one core of a desktop computer (model not given), at the industrial models'
@@ -320,6 +321,7 @@ def main():
     bf = fused_bytes(sc, esz)
     traffic = None
     valu_busy = None
+    valu_insts = None
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     sname = "k_stage_ll" if sc.variant == "LL" else "k_stage_nl"
     kname = "k_step_nl" if fused else sname
@@ -328,6 +330,7 @@ def main():
         if ent and ent.get("kernel_hash") == kernel_source_hash() and ent.get("kernel") == kname:
             traffic = ent.get("bytes_per_launch")
             valu_busy = ent.get("valu_busy")
+            valu_insts = ent.get("valu_insts_per_launch")
     real = "float" if esz == 4 else "double"
     if fused:
         ach = cells * bf / (ms1 * 1e-3) / 1e9
@@ -337,8 +340,14 @@ def main():
                 "step_frac": cells * bf / (wall / args.steps) / 1e9 / HBM_PEAK_GBS,
                 "ms_per_step_with_events": ms_step_ev,
                 # the kernel is bound by vector-ALU issue, not HBM: the VALUBusy
-                # counter of the profiled run of these sources
-                "valu_busy": valu_busy}
+                # counter of the profiled run of these sources, and the counted
+                # VALU instructions per launch over this run's launch time
+                # against the issue rate of 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles
+                "valu_busy": valu_busy,
+                "valu_issue": None if valu_insts is None else {
+                    "achieved": valu_insts / (ms1 * 1e-3) / 1e9, "peak": VALU_ISSUE_PEAK_G,
+                    "unit": "G wave64 VALU instructions/s",
+                    "frac": valu_insts / (ms1 * 1e-3) / 1e9 / VALU_ISSUE_PEAK_G}}
         # the per-stage kernels on the same steps, for comparison
         sim.set_step_kernel(False)
         reset()
