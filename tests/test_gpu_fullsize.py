@@ -45,7 +45,7 @@ def _window_params(sc, J0, J1, I0, I1):
             inflows.append(O.InflowBC(b.side, lo - off, hi - off, O._t(b.t), O._t(b.Q) * frac))
     return O.Params(nx=I1 - I0, ny=J1 - J0, dx=sc.dx, dy=sc.dy, g=sc.g, tol=sc.tol_dry, cfl=sc.cfl,
                     dt_max=sc.dt_max, theta=sc.theta, variant=sc.variant, manning=man,
-                    inflows=inflows, rain=sc.rain)
+                    inflows=inflows, rain=sc.rain, flux=sc.flux)
 
 
 def _check_window(sc, before, after, t, dt, j0, j1, i0, i1, rtol, atol, margin=MARGIN):
@@ -117,9 +117,11 @@ def test_floodplain_full_size_fp64_windows():
     assert wet_seen > 0.2  # the inflow mouth is flooded
 
 
-def test_urban_full_size_fp32_windows():
+@pytest.mark.parametrize("flux", ["HLL", "ROE"])
+def test_urban_full_size_fp32_windows(flux):
     sc = WL.urban()
-    _say("urban 4096 x 4096 FP32: 400 steps, then one step on sampled windows")
+    sc.flux = flux
+    _say("urban 4096 x 4096 FP32 %s: 400 steps, then one step on sampled windows" % flux)
     before, after, t, dt = _run(sc, 400)
     rng = np.random.default_rng(22)
     # a window on a block edge: find a cell whose bed jumps by the block height
