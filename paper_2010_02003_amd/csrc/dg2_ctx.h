@@ -156,8 +156,11 @@ inline Launch stage_launch_of(const dg2_ctx *c) {
 }
 // The fused kernel computes two halo rows of stage 1 per work item, so it
 // takes longer items (about three rounds of its ~3k resident wavefronts).
+// The fused kernel's built-in rows per wavefront: 48 at 4096^2 (about 5 900
+// wavefronts); with the edge tiles' own marches, 48 rows ran 0.6 % faster
+// than 32 and 24.
 inline Launch fused_launch_of(const dg2_ctx *c) {
-  return make_launch(c->cfg.nx, c->cfg.ny, kStripF, c->R_user, c->wpb_user, 8800);
+  return make_launch(c->cfg.nx, c->cfg.ny, kStripF, c->R_user, c->wpb_user, 5800, 48);
 }
 inline Launch launch_of(const dg2_ctx *c) {
   return fused_active(c) ? fused_launch_of(c) : stage_launch_of(c);

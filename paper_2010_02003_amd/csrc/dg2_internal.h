@@ -50,8 +50,9 @@ constexpr int kStripLL = 60;  // output columns per wavefront (halo 2)
 constexpr int kStripF = 60;   // fused NL step: output columns per wavefront (halo 2)
 
 // Work items of a launch over strips of `cols` output columns; R <= 0 picks
-// the built-in rows per wavefront, aiming at about `items` work items.
-Launch make_launch(int nx, int ny, int cols, int R, int wpb, int items);
+// the built-in rows per wavefront, aiming at about `items` work items, with
+// 4 <= R <= rmax.
+Launch make_launch(int nx, int ny, int cols, int R, int wpb, int items, int rmax = 32);
 
 template <typename real>
 hipError_t launch_stage(int stage, int variant, const Scen<real> &s, const Consts &c,

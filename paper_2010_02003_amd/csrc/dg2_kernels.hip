@@ -616,19 +616,24 @@ struct FusedCarry {
 // and columns i0 - 2 .. i0 + 61 (i0 = 60 strip, j1 = j0 + R).  Such a tile has
 // no boundary face, ghost lane, ghost row or clamped column.
 template <typename real>
-__device__ __forceinline__ bool fused_interior(const Scen<real> &s, int strip, int seg, int R) {
+__device__ __forceinline__ bool fused_xin(const Scen<real> &s, int strip) {
+  return strip >= 1 && strip * kStripF + 61 <= s.nx - 1;
+}
+template <typename real>
+__device__ __forceinline__ bool fused_yin(const Scen<real> &s, int seg, int R) {
   const int j0 = seg * R;
-  return strip >= 1 && strip * kStripF + 61 <= s.nx - 1 && j0 >= 2 && j0 + R + 1 <= s.ny - 1;
+  return j0 >= 2 && j0 + R + 1 <= s.ny - 1;
 }
 
 // CHECK: a trial of the stage-1 Courant check.  s.ctrl is then the check's
 // staging block: the launch returns at once unless it is armed, and the
 // Courant minimum of the stage-1 result over the output cells goes to its
 // minbits1 (the new state's minimum and flags to its minbits and flags).
-// EDGE = false: an interior tile (fused_interior); the boundary treatment is
-// compiled out, which leaves the march far fewer live scalars and branches
-// (same arithmetic, bitwise equal results).
-template <typename real, int FLUX, bool down, bool CHECK, bool EDGE>
+// XE / YE: the tile touches the west or east / the south or north grid edge;
+// without them (an interior tile) the march runs two rows per iteration.
+// Dropping a boundary treatment a tile does not need leaves the march fewer
+// live scalars and branches (same arithmetic, bitwise equal results).
+template <typename real, int FLUX, bool down, bool CHECK, bool XE, bool YE>
 __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Consts &c, int strip,
                                                 int seg, int R, int lane) {
   if (CHECK && s.ctrl->aux == 0u) return;
@@ -658,12 +663,12 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
   const int afirst = min(max(jfirst - d, 0), ny - 1);
   const int alast = min(max(jlast + d, 0), ny - 1);
   const int astop = alast + d;
-  const bool own = lane >= 2 && lane <= kStripF + 1 && (!EDGE || i < s.nx);
-  const int ci = !EDGE ? i : (i < 0 ? 0 : (i >= s.nx ? s.nx - 1 : i));
-  const bool mx = EDGE && ((i < 0) || (i >= s.nx));
+  const bool own = lane >= 2 && lane <= kStripF + 1 && (!XE || i < s.nx);
+  const int ci = !XE ? i : (i < 0 ? 0 : (i >= s.nx ? s.nx - 1 : i));
+  const bool mx = XE && ((i < 0) || (i >= s.nx));
   // whether this strip holds the ghost lane west (i = -1) or east (i = nx) of the grid
-  const bool wedge = EDGE && strip == 0;
-  const bool eedge = EDGE && s.nx - strip * kStripF + 2 <= 63;
+  const bool wedge = XE && strip == 0;
+  const bool eedge = XE && s.nx - strip * kStripF + 2 <= 63;
   const real rain = (real)s.ctrl->rain;
   const real gdt = g * dt;
   const real *src = s.U;
@@ -677,12 +682,12 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
   const real qS2 = (real)s.ctrl->qin[2][1], qN2 = (real)s.ctrl->qin[3][1];
   const bool inS = i >= s.seg_first[2] && i <= s.seg_last[2];
   const bool inN = i >= s.seg_first[3] && i <= s.seg_last[3];
-  const bool faceW1 = EDGE && (i == -1) && side_on(kW, qW1);
-  const bool faceW2 = EDGE && (i == -1) && side_on(kW, qW2);
-  const bool faceE1 = EDGE && (i == s.nx - 1) && side_on(kE, qE1);
-  const bool faceE2 = EDGE && (i == s.nx - 1) && side_on(kE, qE2);
-  const bool colS1 = EDGE && side_on(kS, qS1) && inS, colS2 = EDGE && side_on(kS, qS2) && inS;
-  const bool colN1 = EDGE && side_on(kN, qN1) && inN, colN2 = EDGE && side_on(kN, qN2) && inN;
+  const bool faceW1 = XE && (i == -1) && side_on(kW, qW1);
+  const bool faceW2 = XE && (i == -1) && side_on(kW, qW2);
+  const bool faceE1 = XE && (i == s.nx - 1) && side_on(kE, qE1);
+  const bool faceE2 = XE && (i == s.nx - 1) && side_on(kE, qE2);
+  const bool colS1 = YE && side_on(kS, qS1) && inS, colS2 = YE && side_on(kS, qS2) && inS;
+  const bool colN1 = YE && side_on(kN, qN1) && inN, colN2 = YE && side_on(kN, qN2) && inN;
 
   unsigned long long gmask = 0;
   long long gslot = 0;
@@ -694,7 +699,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
   double mloc = __longlong_as_double((long long)kInfBits);
   double m1loc = mloc;
   unsigned flags = 0;
-  if constexpr (!EDGE) {
+  if constexpr (!XE && !YE) {
     // Interior tiles: the row loop written out twice per iteration, with the
     // values carried from row to row in two slots that swap roles, so no
     // register is copied between rows.
@@ -768,7 +773,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
         build_row<real, 2>(rb, r, ny, mx, rain, gdt, tol, kn.B);
       }
       if (r == afirst) {
-        if (EDGE && afirst == jfirst) {
+        if (YE && afirst == jfirst) {
           // the row before the first output row is beyond the grid edge
           Row<real> gh;
           ghost_row_y(kn.B, tol, gh);
@@ -895,7 +900,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
         build_row<real, 2>(rb, r, ny, mx, rain, gdt, tol, nxtB);
       }
       if (r == afirst) {
-        if (EDGE && afirst == jfirst) {
+        if (YE && afirst == jfirst) {
           // the row before the first output row is beyond the grid edge
           Row<real> gh;
           ghost_row_y(nxtB, tol, gh);
@@ -950,7 +955,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
       dCA = dFA;
     }
 
-    if (EDGE && alast == jlast) {
+    if (YE && alast == jlast) {
       // the row after the last output row is beyond the grid edge
       Row<real> gh;
       ghost_row_y(curB, tol, gh);
@@ -988,23 +993,31 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
   }
 }
 
+// One tile of the fused march: the instantiation without the boundary
+// treatment a tile does not need (west/east edge, south/north edge).
+template <typename real, int FLUX, bool down, bool CHECK>
+__device__ __forceinline__ void fused_tile(const Scen<real> &s, const Consts &c, int strip, int seg,
+                                           int R, int lane) {
+  const bool xin = fused_xin(s, strip), yin = fused_yin(s, seg, R);
+  if (xin && yin)
+    march_fused_dir<real, FLUX, down, CHECK, false, false>(s, c, strip, seg, R, lane);
+  else if (yin)
+    march_fused_dir<real, FLUX, down, CHECK, true, false>(s, c, strip, seg, R, lane);
+  else if (xin)
+    march_fused_dir<real, FLUX, down, CHECK, false, true>(s, c, strip, seg, R, lane);
+  else
+    march_fused_dir<real, FLUX, down, CHECK, true, true>(s, c, strip, seg, R, lane);
+}
+
 template <typename real, int FLUX, bool CHECK>
 __global__ void __launch_bounds__(256, 3) k_step_nl(Scen<real> s, Consts c, Launch L) {
   int item;
   if (!stage_item<2>(L, item)) return;
   const int strip = item % L.nstrips, seg = item / L.nstrips;
-  const bool in = fused_interior(s, strip, seg, L.R);
-  if (seg & 1) {
-    if (in)
-      march_fused_dir<real, FLUX, true, CHECK, false>(s, c, strip, seg, L.R, threadIdx.x & 63);
-    else
-      march_fused_dir<real, FLUX, true, CHECK, true>(s, c, strip, seg, L.R, threadIdx.x & 63);
-  } else {
-    if (in)
-      march_fused_dir<real, FLUX, false, CHECK, false>(s, c, strip, seg, L.R, threadIdx.x & 63);
-    else
-      march_fused_dir<real, FLUX, false, CHECK, true>(s, c, strip, seg, L.R, threadIdx.x & 63);
-  }
+  if (seg & 1)
+    fused_tile<real, FLUX, true, CHECK>(s, c, strip, seg, L.R, threadIdx.x & 63);
+  else
+    fused_tile<real, FLUX, false, CHECK>(s, c, strip, seg, L.R, threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------------------
@@ -1318,18 +1331,10 @@ __global__ void __launch_bounds__(256, 3) k_batch_step(const Scen<real> *__restr
     const int strip = __builtin_amdgcn_readfirstlane(items[it].strip);
     const int seg = __builtin_amdgcn_readfirstlane(items[it].seg);
     const Scen<real> s = scens[sid];
-    const bool in = fused_interior(s, strip, seg, R);
-    if (seg & 1) {
-      if (in)
-        march_fused_dir<real, FLUX, true, false, false>(s, c, strip, seg, R, lane);
-      else
-        march_fused_dir<real, FLUX, true, false, true>(s, c, strip, seg, R, lane);
-    } else {
-      if (in)
-        march_fused_dir<real, FLUX, false, false, false>(s, c, strip, seg, R, lane);
-      else
-        march_fused_dir<real, FLUX, false, false, true>(s, c, strip, seg, R, lane);
-    }
+    if (seg & 1)
+      fused_tile<real, FLUX, true, false>(s, c, strip, seg, R, lane);
+    else
+      fused_tile<real, FLUX, false, false>(s, c, strip, seg, R, lane);
   }
 }
 
@@ -1556,7 +1561,7 @@ __global__ void __launch_bounds__(256) k_diag_final(const double *part, int nb, 
 // Launchers
 // ---------------------------------------------------------------------------
 
-Launch make_launch(int nx, int ny, int cols, int R, int wpb, int items) {
+Launch make_launch(int nx, int ny, int cols, int R, int wpb, int items, int rmax) {
   Launch L;
   L.nstrips = (nx + cols - 1) / cols;
   if (R <= 0) {
@@ -1564,7 +1569,7 @@ Launch make_launch(int nx, int ny, int cols, int R, int wpb, int items) {
     // ~3k resident slots, so the last round is short; the halo rows are
     // mostly L2 hits, the work items of one XCD being neighbours)
     long long r = (long long)L.nstrips * ny / items;
-    R = (int)(r < 4 ? 4 : (r > 32 ? 32 : r));
+    R = (int)(r < 4 ? 4 : (r > rmax ? rmax : r));
   }
   if (R > ny) R = ny;
   L.R = R;
