@@ -13,14 +13,20 @@
 //
 // Stage 2 writes U^{n+1} in place over U^n (or into a separate buffer): a
 // lane reads U^n only at the cell it writes, and halo lanes read only the
-// stage-1 planes.  For FP32 DG2-NL the fused step kernel further down runs
-// both stages in one pass, stage 1 a row ahead of stage 2 with its result in
-// registers, and writes the new state to a second buffer.  On request the NL stages also store the wet/dry decision
-// of every result cell, which the adjoint step needs.  Its tail
-// folds the Courant candidate of every new cell into a wave minimum and one
-// atomic per wavefront; a single-thread plan kernel then turns the minimum
-// into the next step size on the device, so queued steps never wait for
-// the host.
+// stage-1 planes.  On request the NL stages also store the wet/dry decision
+// of every result cell, which the adjoint step needs.  Stage 2's tail folds
+// the Courant candidate of every new cell into a wave minimum and one atomic
+// per wavefront; a single-thread plan kernel then turns the minimum into the
+// next step size on the device, so queued steps never wait for the host.
+//
+// For FP32 DG2-NL the fused step kernel further down runs both stages in one
+// pass, stage 1 a row ahead of stage 2 with its result in registers, and
+// writes the new state to a second buffer.
+//
+// Tiles whose halo lies inside the grid run a form of the march with the
+// boundary treatment compiled out (template flags); the fused kernel's
+// interior form also runs two rows per loop iteration.  All forms do the
+// same arithmetic, so results do not depend on which form a cell gets.
 #include <hip/hip_runtime.h>
 
 #include "dg2_internal.h"
