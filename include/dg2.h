@@ -211,9 +211,12 @@ dg2_status dg2_diagnostics(dg2_ctx *ctx, double *mass, double *energy, double *m
 dg2_status dg2_time_kernels(dg2_ctx *ctx, int32_t nsteps, double *ms_stage1, double *ms_stage2,
                             double *ms_step);
 
-/* Launch shape of the stage kernels: rows marched per wavefront (>= 1) and
- * wavefronts per workgroup (1, 2 or 4).  rows <= 0 restores the built-in
- * choice for this grid.  Results do not depend on it. */
+/* Launch shape of the step kernels (the per-stage kernels and the fused step
+ * kernel alike): rows marched per wavefront (>= 1) and wavefronts per
+ * workgroup (1, 2 or 4).  rows <= 0 restores the built-in choice for this
+ * grid and kernel (about 34 000 wavefronts and at most 32 rows for the
+ * per-stage kernels, about 5 800 wavefronts and at most 48 rows for the
+ * fused kernel).  Results do not depend on it. */
 dg2_status dg2_set_launch(dg2_ctx *ctx, int32_t rows_per_wave, int32_t waves_per_block);
 
 /* Stage-1 Courant check (an option, off by default).  The step size comes
