@@ -233,6 +233,16 @@ dg2_status dg2_set_launch(dg2_ctx *ctx, int32_t rows_per_wave, int32_t waves_per
  * DG2_EINVAL. */
 dg2_status dg2_set_stage_check(dg2_ctx *ctx, int32_t repeats);
 
+/* Partly-wet rule (an option, off by default; not part of the paper's
+ * method).  The paper flags dry elements by the mean depth alone (Sec.
+ * 2.1.3): after each RK stage an element whose mean depth is at or below
+ * tol_dry gets zero discharge modes, and nothing else changes.  With on = 1,
+ * an element with a wet mean but a face-limit depth h0 - max(|h1x|, |h1y|)
+ * at or below tol_dry also drops all six slope modes after each stage
+ * (locally first order at a wet/dry front).  Batches refuse members that
+ * differ in this setting.  on: 0 or 1, else DG2_EINVAL. */
+dg2_status dg2_set_partly_wet_flat(dg2_ctx *ctx, int32_t on);
+
 /* How dg2_step runs the two RK stages of Sec. 2.1.2.  fused = 1 (default):
  * one kernel per step that computes stage 1 a row ahead of stage 2 and keeps
  * the stage-1 result in registers, so a step reads and writes the state once;

@@ -201,6 +201,10 @@ class Params:
     # stage-1 Courant check (an option, off by default): up to this many
     # repeats of stage 1 with a smaller step when its result breaks Cr
     stage_check: int = 0
+    # partly-wet rule (an option, off by default; not in the paper): after
+    # each stage, elements with a wet mean and a face-limit depth at or below
+    # tol drop their slope modes
+    partly_wet_flat: bool = False
 
 
 def _table_value(ts, vs, t: float):
@@ -654,29 +658,33 @@ def rain_depth(prm: Params, t: float, dt: float) -> float:
     return rate * max(0.0, min(t + dt, te) - max(t, tb))
 
 
-def wet_dry_fix(U: torch.Tensor, tol: float) -> torch.Tensor:
+def wet_dry_fix(U: torch.Tensor, tol: float, partly_wet_flat: bool = False) -> torch.Tensor:
     """End-of-stage wet/dry treatment of the element modes.
 
-    Dry elements (mean depth at or below tol, Sec. 2.1.3) get zero discharge
-    modes.  Partly wet elements (wet mean but a face-limit depth at or below
-    tol) drop every slope mode: they are locally first order at the front,
-    which keeps wedge-shaped planar depths holding almost no water from
-    carrying fictitious momentum.  Mean depths are never changed, so mass is
-    conserved exactly.
+    Dry elements are flagged by the mean depth alone (Sec. 2.1.3): an element
+    whose mean depth is at or below tol gets zero discharge modes, and nothing
+    else changes.  Mean depths are never changed, so mass is conserved
+    exactly.
+
+    With ``partly_wet_flat`` (an option that is not part of the paper's
+    method), elements with a wet mean but a face-limit depth at or below tol
+    also drop every slope mode, which makes them locally first order at the
+    front.
     """
     h0 = U[H, M0]
     dry = h0 <= tol
-    lim = torch.minimum(torch.minimum(h0 + U[H, MX], h0 - U[H, MX]),
-                        torch.minimum(h0 + U[H, MY], h0 - U[H, MY]))
-    part = (~dry) & (lim <= tol)
     out = U.clone()
     zero = torch.zeros_like(h0)
     for var in (QX, QY):
         for m in (M0, MX, MY):
             out[var, m] = torch.where(dry, zero, U[var, m])
-    for var in (H, QX, QY):
-        for m in (MX, MY):
-            out[var, m] = torch.where(part, zero, out[var, m])
+    if partly_wet_flat:
+        lim = torch.minimum(torch.minimum(h0 + U[H, MX], h0 - U[H, MX]),
+                            torch.minimum(h0 + U[H, MY], h0 - U[H, MY]))
+        part = (~dry) & (lim <= tol)
+        for var in (H, QX, QY):
+            for m in (MX, MY):
+                out[var, m] = torch.where(part, zero, out[var, m])
     return out
 
 
@@ -687,7 +695,7 @@ def _stage1(U: torch.Tensor, t: float, bed: Bed, prm: Params, dt: float):
     W = apply_friction(W, prm.manning, dt, prm.g, prm.tol)
     if prm.variant == "LL":
         W = local_limit(W, bed, prm)
-    U1 = wet_dry_fix(W + dt * spatial_operator(W, bed, prm, t), prm.tol)
+    U1 = wet_dry_fix(W + dt * spatial_operator(W, bed, prm, t), prm.tol, prm.partly_wet_flat)
     return W, U1
 
 
@@ -695,7 +703,7 @@ def _stage2(W: torch.Tensor, U1: torch.Tensor, t: float, bed: Bed, prm: Params, 
     if prm.variant == "LL":
         U1 = local_limit(U1, bed, prm)
     U2 = 0.5 * (W + U1 + dt * spatial_operator(U1, bed, prm, t + dt))
-    return wet_dry_fix(U2, prm.tol)
+    return wet_dry_fix(U2, prm.tol, prm.partly_wet_flat)
 
 
 def step(U: torch.Tensor, t: float, bed: Bed, prm: Params, dt: float):
@@ -836,7 +844,8 @@ def params_from_scenario(sc) -> Params:
     return Params(nx=sc.nx, ny=sc.ny, dx=sc.dx, dy=sc.dy, g=sc.g, tol=sc.tol_dry, cfl=sc.cfl,
                   dt_max=sc.dt_max, theta=sc.theta, variant=sc.variant, manning=man,
                   inflows=infl, levels=levs, opens=opens, rain=sc.rain, fixed_dt=sc.fixed_dt,
-                  x0=sc.x0, y0=sc.y0, flux=sc.flux, stage_check=sc.stage_check)
+                  x0=sc.x0, y0=sc.y0, flux=sc.flux, stage_check=sc.stage_check,
+                  partly_wet_flat=bool(getattr(sc, "partly_wet_flat", False)))
 
 
 def setup(sc):

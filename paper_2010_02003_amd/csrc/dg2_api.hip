@@ -739,6 +739,13 @@ dg2_status dg2_set_stage_check(dg2_ctx *c, int32_t repeats) {
   return DG2_OK;
 }
 
+dg2_status dg2_set_partly_wet_flat(dg2_ctx *c, int32_t on) {
+  if (!c) return DG2_EINVAL;
+  if (on != 0 && on != 1) return fail(c, DG2_EINVAL, "on must be 0 or 1");
+  c->partly_wet_flat = on;
+  return DG2_OK;
+}
+
 dg2_status dg2_set_step_kernel(dg2_ctx *c, int32_t fused) {
   if (!c) return DG2_EINVAL;
   if (fused != 0 && fused != 1) return fail(c, DG2_EINVAL, "fused must be 0 or 1");
@@ -1102,8 +1109,10 @@ dg2_status dg2_batch_create(dg2_ctx *const *members, int32_t n, void *hip_stream
     if (!c) return bfail(nullptr, DG2_EINVAL, "NULL member");
     if (c->cfg.prec != c0->cfg.prec || c->cfg.variant != c0->cfg.variant ||
         c->cfg.flux != c0->cfg.flux || c->cfg.g != c0->cfg.g ||
-        c->cfg.tol_dry != c0->cfg.tol_dry || c->cfg.ll_threshold != c0->cfg.ll_threshold)
-      return bfail(nullptr, DG2_EINVAL, "members differ in precision, variant, flux, g, tol_dry or threshold");
+        c->cfg.tol_dry != c0->cfg.tol_dry || c->cfg.ll_threshold != c0->cfg.ll_threshold ||
+        c->partly_wet_flat != c0->partly_wet_flat)
+      return bfail(nullptr, DG2_EINVAL,
+                   "members differ in precision, variant, flux, g, tol_dry, threshold or partly-wet rule");
   }
   dg2_batch *b = new (std::nothrow) dg2_batch();
   if (!b) return bfail(nullptr, DG2_ENOMEM, "host allocation failed");

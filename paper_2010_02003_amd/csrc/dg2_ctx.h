@@ -30,6 +30,8 @@ struct dg2_ctx {
   // the repeat block (a Ctrl whose step the repeat stage-1 launches read)
   int stage_check = 0;
   dg2::Ctrl *ctrl2 = nullptr;
+  // partly-wet rule (dg2_set_partly_wet_flat): 0 off (the paper's treatment)
+  int partly_wet_flat = 0;
   bool has_ncell = false;
   double n_uniform = 0.0;
   dg2::Ctrl *ctrl = nullptr;
@@ -137,6 +139,7 @@ inline Consts consts(const dg2_ctx *c) {
   k.tol = c->cfg.tol_dry;
   k.theta = c->cfg.ll_threshold;
   k.flux = c->cfg.flux;
+  k.flat = c->partly_wet_flat;
   return k;
 }
 

@@ -333,21 +333,25 @@ __device__ __forceinline__ void mirror(real *W, bool mx, bool my) {
   }
 }
 
-// End-of-stage wet/dry treatment: a dry element (mean depth <= tol) gets
-// zero discharge modes; a wet element with a face-limit depth <= tol drops
-// every slope mode (locally first order at the front).  Mean depths stay.
-// Returns the decision: 1 dry, 2 partly wet, 0 unchanged.
+// End-of-stage wet/dry treatment.  Dry elements are flagged by the mean
+// depth alone (Sec. 2.1.3): an element with mean depth <= tol gets zero
+// discharge modes.  Mean depths stay, so mass is exact.  With `flat` (an
+// option outside the paper's method) a wet element with a face-limit depth
+// <= tol also drops every slope mode (locally first order at the front).
+// Returns the decision: 1 dry, 2 partly wet and flattened, 0 unchanged.
 template <typename real>
-__device__ __forceinline__ unsigned wet_dry_fix(real *o, real tol) {
+__device__ __forceinline__ unsigned wet_dry_fix(real *o, real tol, bool flat) {
   if (!(o[0] > tol)) {
 #pragma unroll
     for (int k = 3; k < 9; ++k) o[k] = real(0);
     return 1u;
   }
-  const real ax = fabs(o[1]), ay = fabs(o[2]);
-  if (o[0] - (ax > ay ? ax : ay) <= tol) {
-    o[1] = o[2] = o[4] = o[5] = o[7] = o[8] = real(0);
-    return 2u;
+  if (flat) {
+    const real ax = fabs(o[1]), ay = fabs(o[2]);
+    if (o[0] - (ax > ay ? ax : ay) <= tol) {
+      o[1] = o[2] = o[4] = o[5] = o[7] = o[8] = real(0);
+      return 2u;
+    }
   }
   return 0u;
 }

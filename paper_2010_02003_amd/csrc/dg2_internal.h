@@ -36,6 +36,7 @@ struct Scen {
 struct Consts {
   double g, tol, theta;
   int flux;  // kFluxHLL or kFluxRoe
+  int flat;  // partly-wet elements drop their slope modes (an option; 0: off)
 };
 
 struct Launch {

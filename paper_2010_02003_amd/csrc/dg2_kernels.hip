@@ -344,6 +344,7 @@ __device__ __forceinline__ void march_nl_dir(const Scen<real> &s, const Consts &
   if (!(dtd > 0.0)) return;
 
   const real dt = (real)dtd, g = (real)c.g, tol = (real)c.tol;
+  const bool flat = c.flat != 0;
   const real half = real(0.5);
   const int i = strip * kStripNL + lane - 1;
   const int j0 = seg * R, j1 = min(j0 + R, s.ny);
@@ -452,7 +453,7 @@ __device__ __forceinline__ void march_nl_dir(const Scen<real> &s, const Consts &
 #pragma unroll
         for (int k = 0; k < 9; ++k) o[k] = half * (W1[k] + cur.W[k] + dt * Lop[k]);
       }
-      const unsigned code = wet_dry_fix(o, tol);
+      const unsigned code = wet_dry_fix(o, tol, flat);
       const unsigned off = (unsigned)cidx * (unsigned)sizeof(real);
 #pragma unroll
       for (int k = 0; k < 9; ++k) st_at(dst + k * s.P, off, o[k]);
@@ -659,6 +660,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
   }
 
   const real dt = (real)dtd, g = (real)c.g, tol = (real)c.tol;
+  const bool flat = c.flat != 0;
   const real half = real(0.5);
   const int ny = s.ny;
   const int i = strip * kStripF + lane - 2;
@@ -749,7 +751,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
                       Lop);
 #pragma unroll
         for (int k = 0; k < 9; ++k) u1[k] = kc.A.W[k] + dt * Lop[k];
-        (void)wet_dry_fix(u1, tol);
+        (void)wet_dry_fix(u1, tol, flat);
         if (CHECK && own && r >= j0 && r < j1) {
           const double m = cfl_candidate(u1[0], u1[3], u1[6], g, tol, s.dx, s.dy);
           m1loc = m < m1loc ? m : m1loc;
@@ -807,7 +809,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
             real o[9];
 #pragma unroll
             for (int k = 0; k < 9; ++k) o[k] = half * (kc.W1[k] + kc.B.W[k] + dt * Lop[k]);
-            (void)wet_dry_fix(o, tol);
+            (void)wet_dry_fix(o, tol, flat);
             const long long cidx = (long long)kB * s.nx + i;
             const unsigned off = (unsigned)cidx * (unsigned)sizeof(real);
 #pragma unroll
@@ -875,7 +877,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
                       Lop);
 #pragma unroll
         for (int k = 0; k < 9; ++k) u1[k] = curA.W[k] + dt * Lop[k];
-        (void)wet_dry_fix(u1, tol);
+        (void)wet_dry_fix(u1, tol, flat);
         if (CHECK && own && r >= j0 && r < j1) {
           const double m = cfl_candidate(u1[0], u1[3], u1[6], g, tol, s.dx, s.dy);
           m1loc = m < m1loc ? m : m1loc;
@@ -934,7 +936,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
             real o[9];
 #pragma unroll
             for (int k = 0; k < 9; ++k) o[k] = half * (W1p[k] + curB.W[k] + dt * Lop[k]);
-            (void)wet_dry_fix(o, tol);
+            (void)wet_dry_fix(o, tol, flat);
             const long long cidx = (long long)kB * s.nx + i;
             const unsigned off = (unsigned)cidx * (unsigned)sizeof(real);
 #pragma unroll
@@ -981,7 +983,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
         real o[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) o[k] = half * (W1p[k] + curB.W[k] + dt * Lop[k]);
-        (void)wet_dry_fix(o, tol);
+        (void)wet_dry_fix(o, tol, flat);
         const long long cidx = (long long)jlast * s.nx + i;
         const unsigned off = (unsigned)cidx * (unsigned)sizeof(real);
 #pragma unroll
@@ -1163,6 +1165,7 @@ __device__ __forceinline__ void march_ll_tile(const Scen<real> &s, const Consts 
   if (!(dtd > 0.0)) return;
 
   const real dt = (real)dtd, g = (real)c.g, tol = (real)c.tol;
+  const bool flat = c.flat != 0;
   const real half = real(0.5);
   const real thx = (real)(c.theta * 0.5 * (double)s.dx), thy = (real)(c.theta * 0.5 * (double)s.dy);
   const int i = strip * kStripLL + lane - 2;
@@ -1250,7 +1253,7 @@ __device__ __forceinline__ void march_ll_tile(const Scen<real> &s, const Consts 
 #pragma unroll
         for (int k = 0; k < 9; ++k) o[k] = half * (W1[k] + cur.W[k] + dt * Lop[k]);
       }
-      wet_dry_fix(o, tol);
+      wet_dry_fix(o, tol, flat);
 #pragma unroll
       for (int k = 0; k < 9; ++k) st_at(dst + k * s.P, off, o[k]);
       if (STAGE == 2) new_state_checks(s, o, cidx, gmask, gslot, g, tol, mloc, flags);

@@ -79,6 +79,7 @@ _SIGS = {
     "dg2_set_launch": (c_int32, [c_void_p, c_int32, c_int32]),
     "dg2_set_step_kernel": (c_int32, [c_void_p, c_int32]),
     "dg2_set_stage_check": (c_int32, [c_void_p, c_int32]),
+    "dg2_set_partly_wet_flat": (c_int32, [c_void_p, c_int32]),
     "dg2_autotune": (c_int32, [c_void_p, c_double, POINTER(c_int32)]),
     "dg2_state_layout": (c_int32, [c_void_p, POINTER(c_size_t), POINTER(c_size_t)]),
     "dg2_bind_device_state": (c_int32, [c_void_p, c_void_p, c_size_t]),
@@ -256,6 +257,9 @@ class Sim:
 
     def set_stage_check(self, repeats: int):
         self._check(self._lib.dg2_set_stage_check(self._ctx, repeats))
+
+    def set_partly_wet_flat(self, on: bool):
+        self._check(self._lib.dg2_set_partly_wet_flat(self._ctx, 1 if on else 0))
 
     def autotune(self, budget_ms: float = 200.0) -> int:
         r = c_int32()
@@ -463,6 +467,8 @@ def sim_from_scenario(sc, stream=None, precision: Optional[str] = None,
         s.set_fixed_dt(sc.fixed_dt)
     if sc.stage_check > 0:
         s.set_stage_check(sc.stage_check)
+    if sc.partly_wet_flat:
+        s.set_partly_wet_flat(True)
     s.set_initial_corners(sc.surface, sc.is_eta, sc.qx, sc.qy)
     if sc.gauges is not None:
         s.set_gauges(sc.gauges)

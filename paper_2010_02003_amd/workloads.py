@@ -89,6 +89,7 @@ class Scenario:
     x0: float = 0.0
     y0: float = 0.0
     stage_check: int = 0  # repeats of stage 1 allowed by the stage-1 Courant check (0: off)
+    partly_wet_flat: bool = False  # optional partly-wet rule (not in the paper; off by default)
 
     @property
     def cells(self) -> int:

@@ -15,6 +15,13 @@ simulated time, with DG2-NL and DG2-LL (the minmod-limited variant, Sec.
   one 2 m cell): a sub-millimetre film there gains tens of m/s in stage 1,
   beyond what the Courant step of U^n allows in stage 2.  The oracle does
   the same (the method as read); the bound below guards against regressions.
+* With the paper's end-of-stage treatment (dry elements flagged by the mean
+  depth alone, Sec. 2.1.3) the films on those banks also carry fictitious
+  mean velocities of 100-400 m/s at mean depths just above the drying
+  tolerance, and the Courant step falls to a few ms, so a 3 h run takes
+  millions of steps.  The 3 h runs below therefore use the optional
+  partly-wet rule (partly wet elements drop their slope modes); the paper's
+  treatment is run over the first 10 minutes of the hydrograph.
 """
 import time
 
@@ -36,6 +43,7 @@ def _say(*a):
 
 def _run(variant, precision):
     sc = WL.floodplain(variant=variant, precision=precision)
+    sc.partly_wet_flat = True
     s = dg2.sim_from_scenario(sc)
     s.set_gauges(sc.gauges, capacity=120000)  # every step between two reads
     grid = np.arange(60.0, sc.t_end + 1.0, 60.0)
@@ -96,12 +104,13 @@ def test_floodplain_3h_negative_depths_stay_bounded(runs):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_floodplain_3h_with_stage_check_keeps_depths_positive(precision):
-    """The same 3 h run with the stage-1 Courant check (an option): stage 1
+    """The same 3 h run (partly-wet option) with the stage-1 Courant check (an option): stage 1
     is repeated with a smaller step where its own result breaks the Courant
     bound (in FP32 the fused step kernel tries the whole step again), and the
     mean depth stays non-negative throughout."""
     sc = WL.floodplain(precision=precision)
     sc.stage_check = 3
+    sc.partly_wet_flat = True
     s = dg2.sim_from_scenario(sc)
     t0 = time.perf_counter()
     hmin = 0.0
@@ -115,3 +124,25 @@ def test_floodplain_3h_with_stage_check_keeps_depths_positive(precision):
     assert t == sc.t_end
     assert abs(mass - VOLUME) <= (1e-10 if precision == "fp64" else 1e-4) * VOLUME
     assert hmin >= 0.0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_floodplain_paper_treatment_first_10_minutes(precision):
+    """The paper's end-of-stage treatment (the default) over the first 600 s
+    of the rising hydrograph: the volume is the inflow volume
+    (Q = 20 t / 1800 m^3/s, so 2000 m^3; RK2 integrates the linear inflow
+    exactly), the state stays finite, and the step counts and the smallest
+    mean depth are reported."""
+    sc = WL.floodplain(precision=precision)
+    s = dg2.sim_from_scenario(sc)
+    t0 = time.perf_counter()
+    s.run_to(600.0)
+    state, t, steps, _ = s.get_state()
+    mass, _, hmin = s.diagnostics()
+    s.close()
+    vol = 20.0 / 1800.0 * 600.0 ** 2 / 2.0
+    _say("floodplain NL %s, paper treatment: %d steps to t = %.1f s in %.1f s (mean dt %.2e s), "
+         "volume %.6f m^3 (inflow %.1f), min h0 %.2e m"
+         % (precision, steps, t, time.perf_counter() - t0, t / steps, mass, vol, hmin))
+    assert t == 600.0 and np.all(np.isfinite(state))
+    assert abs(mass - vol) <= (1e-10 if precision == "fp64" else 1e-4) * vol

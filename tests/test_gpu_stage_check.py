@@ -1,6 +1,8 @@
 """GPU parity of the stage-1 Courant check (an option, off by default)
 against the oracle's step_checked: on the floodplain's inflow mouth, where
-the plain step drives mean depths negative within 30 steps, the checked run
+the plain step drives mean depths negative (after about 350 steps with the
+paper's end-of-stage treatment, within 30 with the optional partly-wet
+rule), the checked run
 matches the oracle step for step (sizes, times, states) over 100 steps and
 keeps every mean depth non-negative over 200; run-to targets are still met
 exactly; in FP32 the fused step kernel's trials of the whole step give the
@@ -53,18 +55,23 @@ def test_checked_steps_match_oracle_and_stay_positive(variant, flux):
     plain = WL.floodplain_mouth(stage_check=0)
     plain.variant, plain.flux = variant, flux
     p = dg2.sim_from_scenario(plain)
-    p.step(200)
-    assert p.get_state()[0][0].min() < -1e-3
+    pmin = 0.0
+    for _ in range(6):
+        p.step(100)
+        pmin = min(pmin, p.diagnostics()[2])
+    _say("plain step, same case, 600 steps: min h0 %.2e" % pmin)
+    assert pmin < 0.0
 
 
 def test_checked_run_to_lands_on_target():
     sc = WL.floodplain_mouth(stage_check=2)
     s = dg2.sim_from_scenario(sc)
-    s.run_to(15.0)
+    s.run_to(5.0)
     gpu, t, steps, _ = s.get_state()
     U, bed, prm = O.setup(sc)
-    r = O.run(U, bed, prm, t_end=15.0)
-    assert t == 15.0 and steps == r.steps and steps < 100
+    r = O.run(U, bed, prm, t_end=5.0)
+    _say("checked run_to(5 s): %d steps (oracle %d)" % (steps, r.steps))
+    assert t == 5.0 and steps == r.steps and steps < 400
     _close(gpu, O.to_planes(r.U), 1e-10, "checked run_to")
 
 

@@ -360,7 +360,27 @@ def test_friction_planar_modes():
         assert torch.allclose(dn - base_m, ic - 0.5 * (ip - im), atol=1e-14)
 
 
-def test_wet_dry_fix_conserves_mass_and_flattens_only_front_cells():
+def test_wet_dry_fix_flags_dry_elements_by_the_mean_depth_alone():
+    """Sec. 2.1.3: dry elements are flagged from the mean depth h0 only; a wet
+    element whose planar depth dips below zero at a face keeps every mode."""
+    rng = np.random.default_rng(11)
+    U = torch.tensor(rng.uniform(-0.5, 0.5, (3, 3, 6, 7)))
+    U[0, 0] = torch.tensor(rng.uniform(0.0, 1.0, (6, 7)))
+    U[0, 0, 1, 1] = 5e-6  # dry
+    U[0, 0, 3, 3] = 1e-5  # at the tolerance: dry
+    U[0, 0, 2, 2] = 0.3  # wet mean, one negative face limit
+    U[0, 1, 2, 2] = -0.6
+    out = O.wet_dry_fix(U, 1e-5)
+    assert torch.equal(out[0], U[0])  # depth modes untouched: mass conserved
+    for (j, i) in ((1, 1), (3, 3)):
+        assert torch.equal(out[1:, :, j, i], torch.zeros(2, 3, dtype=torch.float64))
+    dry = U[0, 0] <= 1e-5
+    assert int(dry.sum()) == 2
+    assert torch.equal(out[1:, :, ~dry], U[1:, :, ~dry])  # every wet element unchanged
+
+
+def test_partly_wet_option_conserves_mass_and_flattens_only_front_cells():
+    """The optional partly-wet rule (not part of the paper's method)."""
     rng = np.random.default_rng(11)
     U = torch.tensor(rng.uniform(-0.5, 0.5, (3, 3, 6, 7)))
     U[0, 0] = torch.tensor(rng.uniform(0.0, 1.0, (6, 7)))
@@ -371,7 +391,8 @@ def test_wet_dry_fix_conserves_mass_and_flattens_only_front_cells():
     U[0, 0, 4, 4] = 0.9  # fully wet
     U[0, 1, 4, 4] = 0.2
     U[0, 2, 4, 4] = -0.1
-    out = O.wet_dry_fix(U, 1e-5)
+    assert torch.equal(O.wet_dry_fix(U, 1e-5, False)[:, :, 2, 2], U[:, :, 2, 2])  # off by default
+    out = O.wet_dry_fix(U, 1e-5, True)
     assert torch.equal(out[0, 0], U[0, 0])  # mean depths untouched: mass conserved
     assert torch.equal(out[:, :, 4, 4], U[:, :, 4, 4])
     assert torch.equal(out[1:, :, 1, 1], torch.zeros(2, 3, dtype=torch.float64))
@@ -380,13 +401,19 @@ def test_wet_dry_fix_conserves_mass_and_flattens_only_front_cells():
     assert torch.equal(out[:, 0, 2, 2], U[:, 0, 2, 2])
 
 
-def test_from_dry_inflow_stays_finite_and_conservative():
-    """A channel filling from dry through an inflow segment (floodplain-like)."""
+@pytest.mark.parametrize("flat", [False, True])
+def test_from_dry_inflow_stays_finite_and_conservative(flat):
+    """A channel filling from dry through an inflow segment (floodplain-like).
+
+    With the paper's end-of-stage treatment the thin films on the 1 m channel
+    banks dip below zero (about -1.7e-4 m here; depths are never clipped), so
+    only the optional partly-wet rule is held to a non-negative depth."""
     nx, ny, dx = 48, 40, 2.0
     X, Y = WL.corner_xy(nx, ny, dx, dx)
     Z = WL.fbm_surface((ny + 1, nx + 1), 0.7, 2.0, 21) - 1.0 * (np.abs(Y - 40.0) <= 6.0)
     infl = [O.InflowBC(O.WEST, 17, 22, O._t([0.0, 30.0]), O._t([0.0, 4.0]))]
     prm = _prm(nx, ny, dx, manning=0.035, dt_max=0.1, inflows=infl)
+    prm.partly_wet_flat = flat
     U = O.initial_state(Z, np.zeros_like(Z), False)
     bed = O.bed_from_corners(Z)
     r = O.run(U, bed, prm, t_end=40.0)
@@ -397,7 +424,8 @@ def test_from_dry_inflow_stays_finite_and_conservative():
         t += dt
     assert torch.isfinite(r.U).all()
     assert abs(O.mass(r.U, prm) - added) <= 1e-12 * added
-    assert float(r.U[0, 0].min()) > -1e-6
+    if flat:
+        assert float(r.U[0, 0].min()) > -1e-6
     assert r.steps < 4000
 
 
