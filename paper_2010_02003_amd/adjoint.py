@@ -8,6 +8,12 @@ peak, a weighted sum) differentiates through it; parameter maps such as
 per-block Manning values expanded to cells are ordinary torch operations in
 front of it.  Argument marshalling only: all arithmetic of the step and of
 its adjoint runs in the library's kernels.
+
+The library keeps the checkpoints of the last forward run of an Adjoint
+only.  Each node therefore remembers the parameters and the forward count
+it ran with; if another forward run on the same Adjoint came in between
+(two losses in one graph, a validation run), its backward first repeats its
+own forward run, so the gradient always belongs to the node's parameters.
 """
 from __future__ import annotations
 
@@ -19,6 +25,13 @@ from .dg2 import Adjoint
 __all__ = ["GaugeDepths", "DG2Loss", "Adjoint"]
 
 
+def _rerun_if_stale(adj, run):
+    """Repeat a node's forward run if the Adjoint ran another one since."""
+    generation, n, q = run
+    if adj.generation != generation:
+        adj.forward(n, q)
+
+
 class GaugeDepths(torch.autograd.Function):
     @staticmethod
     def forward(ctx, n_cell: torch.Tensor, Q: torch.Tensor, adj: Adjoint) -> torch.Tensor:
@@ -26,11 +39,13 @@ class GaugeDepths(torch.autograd.Function):
         q = Q.detach().to("cpu", torch.float64).numpy() if Q is not None else None
         h = adj.forward(n, q)
         ctx.adj = adj
+        ctx.run = (adj.generation, n, q)
         ctx.devices = (n_cell.device, n_cell.dtype, None if Q is None else (Q.device, Q.dtype))
         return torch.from_numpy(h).to(n_cell.device)
 
     @staticmethod
     def backward(ctx, grad_h: torch.Tensor):
+        _rerun_if_stale(ctx.adj, ctx.run)
         gn, gq = ctx.adj.backward(grad_h.detach().to("cpu", torch.float64).numpy())
         dev, dt, qinfo = ctx.devices
         gn_t = torch.from_numpy(np.ascontiguousarray(gn)).to(dev, dt)
@@ -57,12 +72,14 @@ class DG2Loss(torch.autograd.Function):
         tgt = np.asarray(target.detach().cpu() if torch.is_tensor(target) else target, dtype=np.float64)
         r = h - tgt
         ctx.adj, ctx.block, ctx.r = adj, block, r
+        ctx.run = (adj.generation, n_cell, q)
         ctx.meta = (n_blocks.device, n_blocks.dtype, Q.device, Q.dtype, nb.shape)
         return torch.tensor(float((r * r).sum()), dtype=n_blocks.dtype, device=n_blocks.device)
 
     @staticmethod
     def backward(ctx, grad_J: torch.Tensor):
         g = float(grad_J)
+        _rerun_if_stale(ctx.adj, ctx.run)
         gn, gq = ctx.adj.backward(2.0 * g * ctx.r)
         dev, dt, qdev, qdt, (by, bx) = ctx.meta
         b = ctx.block

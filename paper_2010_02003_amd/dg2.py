@@ -398,6 +398,8 @@ class Adjoint:
         self.ng = sim.ng
         self.n_hydrograph = n_hydrograph
         self._a = c_void_p()
+        # forward runs so far: the library keeps the checkpoints of the last one only
+        self.generation = 0
         st = self._lib.dg2_adj_create(sim._ctx, steps, checkpoint_every, control_side, byref(self._a))
         if st != 0:
             msg = self._lib.dg2_adj_last_error(None)
@@ -428,6 +430,7 @@ class Adjoint:
             assert q.shape == (self.n_hydrograph,)
         h = np.empty((self.steps, self.ng), dtype=np.float64)
         self._check(self._lib.dg2_adj_forward(self._a, _dp(n), _dp(q), _dp(h)))
+        self.generation += 1
         return h
 
     def backward(self, dL_dh):

@@ -102,11 +102,19 @@ def _scenario_level_floodplain():
     return sc
 
 
-@pytest.mark.parametrize("make,T", [(_scenario_level_channel, 5.0), (_scenario_open_stoker, 8.0),
-                                    (_scenario_level_floodplain, 120.0)])
-def test_boundary_runs_match_oracle(make, T):
+# The level-fed floodplain wets a dry fBm bed; with the paper's end-of-stage
+# treatment its thin films amplify round-off (the oracle with the level
+# changed by one part in 1e14 agrees with itself to 8e-13 after 20 s, 6e-7
+# after 40 s), so it is compared over 20 s, and over the whole 120 s with the
+# optional partly-wet rule.
+@pytest.mark.parametrize("make,T,flat", [(_scenario_level_channel, 5.0, False),
+                                         (_scenario_open_stoker, 8.0, False),
+                                         (_scenario_level_floodplain, 20.0, False),
+                                         (_scenario_level_floodplain, 120.0, True)])
+def test_boundary_runs_match_oracle(make, T, flat):
     sc = make()
-    _say("boundary run", sc.name, "to", T)
+    sc.partly_wet_flat = flat
+    _say("boundary run", sc.name, "to", T, "partly-wet rule", flat)
     s = dg2.sim_from_scenario(sc)
     s.run_to(T)
     gpu, t, step, _ = s.get_state()
