@@ -203,6 +203,29 @@ dg2_status dg2_read_gauges(dg2_ctx *ctx, double *out, double *t, int32_t max_sam
  * element) and the smallest mean depth.  Any pointer may be NULL. */
 dg2_status dg2_diagnostics(dg2_ctx *ctx, double *mass, double *energy, double *min_h);
 
+/* The integrals of dg2_diagnostics for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops): no context, no
+ * allocation, no host copy and no synchronisation.  Queues two kernels on
+ * hip_stream (NULL: the null stream) and returns.
+ *   state: 9 device planes of the modes (plane order above), each of
+ *          plane_stride >= nx*ny elements, row-major with x fastest;
+ *   bed:   3 device planes z0, z1x, z1y with the same plane stride;
+ *   prec:  DG2_FP64 (double planes) or DG2_FP32 (float planes);
+ *   out4:  device doubles, written when the kernels run: mass (m^3, Eq. 11),
+ *          energy (Eq. 12, as dg2_diagnostics), smallest mean depth, and the
+ *          number of NaN mean depths.
+ * Buffers are borrowed for the duration of the queued work.  The partial
+ * sums live in a static device array of 1024 records of 4 doubles (32 KiB)
+ * that each GPU holds until the process ends, for any grid size; every call
+ * on one GPU uses the same array, so calls that overlap on one GPU (two
+ * streams, two threads) race, and must be ordered by the caller.  Errors:
+ * DG2_EINVAL for NULL or misaligned pointers, nx or ny < 1, a stride below
+ * nx*ny, a bad prec or non-positive dx, dy, g, tol_dry; DG2_EHIP if a launch
+ * fails.  The message is dg2_last_error(NULL). */
+dg2_status dg2_diagnostics_noalloc(const void *state, const void *bed, int32_t nx, int32_t ny,
+                                   int64_t plane_stride, int32_t prec, double dx, double dy, double g,
+                                   double tol_dry, double *out4, void *hip_stream);
+
 /* Time nsteps steps with HIP events on the context's stream, one event pair
  * per kernel: average milliseconds of the stage-1 kernel, the stage-2 kernel
  * and of a whole step (any pointer may be NULL).  When the fused step kernel

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <limits>
@@ -310,6 +311,13 @@ dg2_status dg2_create(const dg2_config *cfg, dg2_ctx **out) {
     e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e != hipSuccess) return bail(hipfail(c, e, "stream create"));
     c->own_stream = true;
+  }
+  // set-up of the allocation-free diagnostics: the device address of its
+  // scratch on this device (looked up once per device)
+  {
+    double *records = nullptr;
+    e = scratch_records(&records);
+    if (e != hipSuccess) return bail(hipfail(c, e, "scratch address"));
   }
   const size_t pb = (size_t)c->P * c->esz;
   dg2_status s;
@@ -695,6 +703,47 @@ dg2_status dg2_diagnostics(dg2_ctx *c, double *mass, double *energy, double *min
   if (s != DG2_OK) return s;
   if (h[3] > 0) return fail(c, DG2_ENUMERIC, "NaN in the state");
   return latched(c);
+}
+
+dg2_status dg2_diagnostics_noalloc(const void *state, const void *bed, int32_t nx, int32_t ny,
+                                   int64_t plane_stride, int32_t prec, double dx, double dy, double g,
+                                   double tol_dry, double *out4, void *hip_stream) {
+  if (!state || !bed || !out4) return fail(nullptr, DG2_EINVAL, "state, bed and out4 must not be NULL");
+  if (prec != DG2_FP64 && prec != DG2_FP32) return fail(nullptr, DG2_EINVAL, "bad prec");
+  const size_t esz = prec == DG2_FP32 ? 4 : 8;
+  if (((uintptr_t)state | (uintptr_t)bed) % esz != 0 || (uintptr_t)out4 % 8 != 0)
+    return fail(nullptr, DG2_EINVAL, "misaligned pointer");
+  if (nx < 1 || ny < 1) return fail(nullptr, DG2_EINVAL, "nx and ny must be >= 1");
+  if (plane_stride < (int64_t)nx * ny) return fail(nullptr, DG2_EINVAL, "plane_stride must be >= nx*ny");
+  if (!(dx > 0) || !(dy > 0) || !(g > 0) || !(tol_dry > 0) || !std::isfinite(dx) || !std::isfinite(dy))
+    return fail(nullptr, DG2_EINVAL, "dx, dy, g and tol_dry must be positive");
+  double *records = nullptr;
+  hipError_t e = scratch_records(&records);
+  if (e != hipSuccess) return hipfail(nullptr, e, "scratch address");
+  Consts k{};
+  k.g = g;
+  k.tol = tol_dry;
+  const double area = dx * dy;
+  const hipStream_t st = (hipStream_t)hip_stream;
+  if (prec == DG2_FP32) {
+    Scen<float> sc{};
+    sc.U = (const float *)state;
+    sc.z = (const float *)bed;
+    sc.nx = nx;
+    sc.ny = ny;
+    sc.P = plane_stride;
+    e = launch_diag<float>(sc, k, records, kScratchRecords, out4, st, area, 0.25 * area);
+  } else {
+    Scen<double> sc{};
+    sc.U = (const double *)state;
+    sc.z = (const double *)bed;
+    sc.nx = nx;
+    sc.ny = ny;
+    sc.P = plane_stride;
+    e = launch_diag<double>(sc, k, records, kScratchRecords, out4, st, area, 0.25 * area);
+  }
+  if (e != hipSuccess) return hipfail(nullptr, e, "diagnostics launch");
+  return DG2_OK;
 }
 
 dg2_status dg2_time_kernels(dg2_ctx *c, int32_t nsteps, double *ms1, double *ms2, double *msstep) {

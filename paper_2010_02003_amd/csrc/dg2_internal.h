@@ -84,9 +84,17 @@ hipError_t launch_cfl(const Scen<real> &s, const Consts &c, hipStream_t st,
 hipError_t launch_stage_check(Ctrl *ctrl, Ctrl *rep, const PlanArgs &p, int first, int last,
                               hipStream_t st);
 
+// Mass, energy and minimum depth sums of s.U into out4 (4 doubles, mass
+// scaled by sm and energy by se), via nblocks per-block records in partials.
 template <typename real>
 hipError_t launch_diag(const Scen<real> &s, const Consts &c, double *partials, int nblocks,
-                       double *out4, hipStream_t st);
+                       double *out4, hipStream_t st, double sm = 1.0, double se = 1.0);
+
+// Records (4 doubles each) of the allocation-free diagnostics' scratch.
+constexpr int kScratchRecords = 1024;
+// Device address of that scratch on the current device (looked up once per
+// device with hipGetSymbolAddress).
+hipError_t scratch_records(double **ptr);
 
 // Batched ensemble: items are (scenario, strip, segment, pad) int quadruples.
 template <typename real>

@@ -29,6 +29,8 @@
 // same arithmetic, so results do not depend on which form a cell gets.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "dg2_internal.h"
 
 namespace dg2 {
@@ -1545,7 +1547,10 @@ __global__ void __launch_bounds__(256) k_diag(Scen<real> s, Consts c, double *pa
   }
 }
 
-__global__ void __launch_bounds__(256) k_diag_final(const double *part, int nb, double *out) {
+// Sums the per-block records and scales the two sums (mass by sm, energy by
+// se; the library's own diagnostics pass 1 and scale on the host).
+__global__ void __launch_bounds__(256) k_diag_final(const double *part, int nb, double *out, double sm,
+                                                    double se) {
   __shared__ double sh[4][256];
   const int t = threadIdx.x;
   double a = 0.0, b = 0.0, m = __longlong_as_double((long long)kInfBits), d = 0.0;
@@ -1570,8 +1575,8 @@ __global__ void __launch_bounds__(256) k_diag_final(const double *part, int nb, 
     __syncthreads();
   }
   if (t == 0) {
-    out[0] = sh[0][0];
-    out[1] = sh[1][0];
+    out[0] = sh[0][0] * sm;
+    out[1] = sh[1][0] * se;
     out[2] = sh[2][0];
     out[3] = sh[3][0];
   }
@@ -1723,10 +1728,43 @@ hipError_t launch_stage_check(Ctrl *ctrl, Ctrl *rep, const PlanArgs &p, int firs
 
 template <typename real>
 hipError_t launch_diag(const Scen<real> &s, const Consts &c, double *partials, int nblocks,
-                       double *out4, hipStream_t st) {
+                       double *out4, hipStream_t st, double sm, double se) {
   hipLaunchKernelGGL((k_diag<real>), dim3(nblocks), dim3(256), 0, st, s, c, partials);
-  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, st, partials, nblocks, out4);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, st, partials, nblocks, out4, sm, se);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free diagnostics entry point: the per-block
+// records of the reduction (4 doubles per block), in a file-scope device
+// array that each GPU holds once for the life of the process.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in); it uses the device address that hipGetSymbolAddress returns,
+// looked up once per device with that device current and kept here.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kScratchRecords * 4];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_records(double **ptr) {
+  *ptr = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double *)p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 template <typename real, int STAGE, int FLUX>
@@ -1861,9 +1899,9 @@ template hipError_t launch_cfl<double>(const Scen<double> &, const Consts &, hip
                                        unsigned long long *);
 template hipError_t launch_cfl<float>(const Scen<float> &, const Consts &, hipStream_t, const Ctrl *,
                                       unsigned long long *);
-template hipError_t launch_diag<double>(const Scen<double> &, const Consts &, double *, int,
-                                        double *, hipStream_t);
-template hipError_t launch_diag<float>(const Scen<float> &, const Consts &, double *, int,
-                                       double *, hipStream_t);
+template hipError_t launch_diag<double>(const Scen<double> &, const Consts &, double *, int, double *,
+                                        hipStream_t, double, double);
+template hipError_t launch_diag<float>(const Scen<float> &, const Consts &, double *, int, double *,
+                                       hipStream_t, double, double);
 
 }  // namespace dg2

@@ -74,6 +74,8 @@ _SIGS = {
     "dg2_read_gauges": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double), c_int32,
                                   POINTER(c_int32)]),
     "dg2_diagnostics": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
+    "dg2_diagnostics_noalloc": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int64, c_int32, c_double,
+                                          c_double, c_double, c_double, c_void_p, c_void_p]),
     "dg2_time_kernels": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double),
                                    POINTER(c_double)]),
     "dg2_set_launch": (c_int32, [c_void_p, c_int32, c_int32]),
@@ -320,6 +322,21 @@ class Sim:
 
     def bind_device_state(self, ptr: Optional[int], nbytes: int = 0):
         self._check(self._lib.dg2_bind_device_state(self._ctx, ptr, nbytes))
+
+
+def diagnostics_noalloc(state_ptr: int, bed_ptr: int, nx: int, ny: int, plane_stride: int,
+                        precision: str, dx: float, dy: float, g: float, tol_dry: float,
+                        out4_ptr: int, stream_ptr: Optional[int] = None):
+    """``dg2_diagnostics_noalloc``: queue the mass/energy/min-depth reduction of
+    device planes into four device doubles at ``out4_ptr`` (pointers are
+    device addresses, e.g. ``tensor.data_ptr()``).  Allocates nothing."""
+    lib = load_library()
+    st = lib.dg2_diagnostics_noalloc(state_ptr, bed_ptr, nx, ny, plane_stride,
+                                     1 if precision == "fp32" else 0, dx, dy, g, tol_dry,
+                                     out4_ptr, stream_ptr)
+    if st != 0:
+        msg = lib.dg2_last_error(None)
+        raise DG2Error(st, msg.decode() if msg else "")
 
 
 class Batch:
