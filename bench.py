@@ -13,9 +13,10 @@ DG2-NL, 2000 steps: the configuration whose working set (>1 GB) exceeds the
 256 MB Infinity Cache, so that its bandwidth is HBM bandwidth.
 
 One step is one DG2 time step (two RK stages plus the device-side step
-planner).  The workload is first advanced, untimed, to a simulated time of
---spinup-s seconds (40 s by default: the rain film then covers every street
-and roof, so every wet-cell branch of the step does its work), then W
+planner).  The workload is first advanced, untimed and with the per-stage
+kernels, to a simulated time of --spinup-s seconds (40 s by default: the
+rain film then covers every street and roof, so every wet-cell branch of
+the step does its work), then W
 warm-up steps run.  The timed region is the next K steps, queued back to
 back on the library's stream.  The K steps after those are run with HIP
 events around every kernel launch on that stream, for the per-kernel
@@ -297,10 +298,15 @@ def main():
     sim.set_step_kernel(args.step_kernel == "fused")
 
     # spin-up into the wet steady state, then warm-up steps; nothing is reset,
-    # so every timed step below runs on a wet domain
+    # so every timed step below runs on a wet domain.  The spin-up runs on
+    # the per-stage kernels (bitwise the same states as the fused kernel), so
+    # that every launch of the fused step kernel in a profile of this command
+    # belongs to the wet steady state.
     if args.spinup_s > 0:
+        sim.set_step_kernel(False)
         sim.run_to(args.spinup_s)
         sim.sync()
+        sim.set_step_kernel(args.step_kernel == "fused")
     if args.warmup > 0:
         sim.step(args.warmup)
         sim.sync()

@@ -55,20 +55,42 @@ struct PlanArgs {
   int hist_len;
 };
 
-// Arithmetic kernels by precision.  FP64 keeps correctly rounded division,
-// square root and rcbrt.  FP32 uses the hardware reciprocal, square root,
-// exp2 and log2 (about 1 ulp): every operand here is a normal number (depths
-// above the drying tolerance, positive wave-speed gaps), so no range scaling
-// is needed, and the FP32 path is held to a stated depth error instead of
-// bitwise agreement.
+// Arithmetic kernels by precision.  Every operand here is a positive normal
+// number (depths above the drying tolerance, positive wave-speed gaps) or,
+// for the square root, zero, so no range scaling or special-case handling is
+// needed.  FP32 uses the hardware reciprocal, square root, exp2 and log2
+// (about 1 ulp); the FP32 path is held to a stated depth error.  FP64
+// refines the hardware estimates by Newton's method instead of calling the
+// correctly rounded division and square root sequences (whose scaling and
+// fix-up steps cost a third of the FP64 stage kernels' time): the
+// reciprocal takes two Newton steps on the estimate of v_rcp_f64, a quotient
+// one correction of a * (1/b), the square root one Newton step on the
+// estimate of v_sqrt_f64; each result is within an ulp or two of the
+// correctly rounded one.  rcbrt stays the library's.
 template <typename real> __device__ __forceinline__ real dsqrt(real x);
-template <> __device__ __forceinline__ double dsqrt<double>(double x) { return sqrt(x); }
+template <> __device__ __forceinline__ double dsqrt<double>(double x) {
+  // y + (x - y^2) / (2 y) on the hardware estimate y
+  const double y = __builtin_amdgcn_sqrt(x);
+  const double r = __builtin_amdgcn_rcp(y);
+  const double e = __builtin_fma(-y, y, x);
+  return x > 0.0 ? __builtin_fma(0.5 * e, r, y) : 0.0;
+}
 template <> __device__ __forceinline__ float dsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <typename real> __device__ __forceinline__ real drcp(real x);
-template <> __device__ __forceinline__ double drcp<double>(double x) { return 1.0 / x; }
+template <> __device__ __forceinline__ double drcp<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
 template <> __device__ __forceinline__ float drcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <typename real> __device__ __forceinline__ real ddiv(real a, real b);
-template <> __device__ __forceinline__ double ddiv<double>(double a, double b) { return a / b; }
+template <> __device__ __forceinline__ double ddiv<double>(double a, double b) {
+  const double r = drcp<double>(b);
+  const double q = a * r;
+  return __builtin_fma(__builtin_fma(-b, q, a), r, q);
+}
 template <> __device__ __forceinline__ float ddiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 // h^(-7/3) for a depth h above the drying tolerance
 template <typename real> __device__ __forceinline__ real pow_m7_3(real h);
@@ -104,14 +126,10 @@ template <typename real>
 __device__ __forceinline__ void dummy_limit(real h, real qx, real qy, real tol, real &hs, real &u,
                                             real &v) {
   hs = h > real(0) ? h : real(0);
-  if (h > tol) {
-    const real r = drcp(h);
-    u = qx * r;
-    v = qy * r;
-  } else {
-    u = real(0);
-    v = real(0);
-  }
+  // one select on the reciprocal zeroes both velocities of a dry limit
+  const real r = h > tol ? drcp(h) : real(0);
+  u = qx * r;
+  v = qy * r;
 }
 
 // HLL flux through a face with normal velocity u and tangential velocity v.
@@ -239,18 +257,13 @@ __device__ __forceinline__ void flux_x(real h, real qx, real qy, real g, real to
                                        real &F1, real &F2) {
   const real hp = h > real(0) ? h : real(0);
   const real pres = real(0.5) * g * hp * hp;
-  if (h > tol) {
-    const real r = drcp(h);
-    const real u = qx * r, v = qy * r;
-    const real q = hp * u;
-    F0 = q;
-    F1 = q * u + pres;
-    F2 = q * v;
-  } else {
-    F0 = real(0);
-    F1 = pres;
-    F2 = real(0);
-  }
+  // a dry point has zero velocities: zeroing the reciprocal zeroes u, v, q
+  const real r = h > tol ? drcp(h) : real(0);
+  const real u = qx * r, v = qy * r;
+  const real q = hp * u;
+  F0 = q;
+  F1 = q * u + pres;
+  F2 = q * v;
 }
 
 // Physical y-flux at a point, returned as [mass, x-momentum, y-momentum].
@@ -259,18 +272,12 @@ __device__ __forceinline__ void flux_y(real h, real qx, real qy, real g, real to
                                        real &G1, real &G2) {
   const real hp = h > real(0) ? h : real(0);
   const real pres = real(0.5) * g * hp * hp;
-  if (h > tol) {
-    const real r = drcp(h);
-    const real u = qx * r, v = qy * r;
-    const real q = hp * v;
-    G0 = q;
-    G1 = q * u;
-    G2 = q * v + pres;
-  } else {
-    G0 = real(0);
-    G1 = real(0);
-    G2 = pres;
-  }
+  const real r = h > tol ? drcp(h) : real(0);
+  const real u = qx * r, v = qy * r;
+  const real q = hp * v;
+  G0 = q;
+  G1 = q * u;
+  G2 = q * v + pres;
 }
 
 // Implicit friction increment at one point.  The split friction ODE

@@ -68,11 +68,12 @@ def test_roe_dam_break_500_steps_fp64_matches_oracle_to_1e10():
     assert 0.0 < diff < 5e-2
 
 
-@pytest.mark.parametrize("flat,T", [(False, 8.0), (True, 20.0)])
+@pytest.mark.parametrize("flat,T", [(False, 8.0), (True, 6.0)])
 def test_roe_from_dry_channel_matches_oracle(flat, T):
-    """Horizons as for HLL: with the paper's end-of-stage treatment the
-    oracle, with the inflow changed by one part in 1e14, agrees with itself
-    to 2e-13 after 8 s (2e-9 after 12 s)."""
+    """Horizons where the oracle, with the inflow changed by one part in
+    1e14, still agrees with itself far below the bar: with the paper's
+    end-of-stage treatment 2e-13 after 8 s (2e-9 after 12 s); with the
+    partly-wet option 2e-15 after 6 s (2e-12 after 8 s, 9e-9 after 20 s)."""
     nx, ny, dx = 48, 40, 2.0
     X, Y = WL.corner_xy(nx, ny, dx, dx)
     Z = WL.fbm_surface((ny + 1, nx + 1), 0.7, 2.0, 21) - 1.0 * (np.abs(Y - 40.0) <= 6.0)
