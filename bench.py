@@ -418,13 +418,23 @@ def main():
         "paper_runtimes": PAPER_RUNTIMES,
     }
     if args.copy_mib > 0:
+        # three plain device copies: the reference reading of the HBM traffic
+        # counters, and the copy bandwidth this box attains (read + written
+        # bytes over the HIP-event time of the second and third copy)
         n = args.copy_mib * (1 << 20) // 4
         a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
-        for _ in range(3):
+        b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(2):
             b.copy_(a)
+        e1.record()
         torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 2
         out["copy_calibration_mib"] = args.copy_mib
+        out["copy_bandwidth"] = {"GB/s": 2 * n * 4 / (ms * 1e-3) / 1e9, "ms_per_copy": ms,
+                                 "frac": 2 * n * 4 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     if not args.no_ensemble:
         out["batched"] = ensemble_leg()
     if not args.no_adjoint:

@@ -275,10 +275,25 @@ dg2_status dg2_set_partly_wet_flat(dg2_ctx *ctx, int32_t on);
  * other values. */
 dg2_status dg2_set_step_kernel(dg2_ctx *ctx, int32_t fused);
 
-/* Pick the launch shape by timing candidates on copies of the current state
- * (the state is restored afterwards); budget_ms bounds the time spent.  The
- * chosen rows-per-wave is returned in *rows (may be NULL). */
+/* Pick the launch shape (rows marched per wavefront x wavefronts per
+ * workgroup) by timing candidates, the built-in shape first, on copies of
+ * the current state (the state is restored afterwards); budget_ms bounds
+ * the time spent.  With a tune cache (dg2_set_tune_cache) a shape stored for
+ * the same key (GPU architecture, precision, variant, flux, fused or
+ * per-stage kernels, grid size rounded up to powers of two) is taken without
+ * timing; otherwise the chosen shape is stored there.  The chosen
+ * rows-per-wave is returned in *rows (may be NULL).  The shape never changes
+ * results.  DG2_EINVAL if the cache file cannot be written. */
 dg2_status dg2_autotune(dg2_ctx *ctx, double budget_ms, int32_t *rows);
+
+/* File of the autotuner's cache (a small JSON object, created if missing);
+ * NULL or "" turns the cache off (the default).  Host arrays are copied. */
+dg2_status dg2_set_tune_cache(dg2_ctx *ctx, const char *path);
+
+/* Current launch shape: rows per wavefront, wavefronts per workgroup, and
+ * whether the last dg2_autotune took it from the cache (1) or not (0).
+ * Any pointer may be NULL. */
+dg2_status dg2_get_launch(const dg2_ctx *ctx, int32_t *rows, int32_t *waves, int32_t *from_cache);
 
 /* Bytes of device memory a state needs (9 planes, padded plane stride) and
  * the plane stride in elements; for dg2_bind_device_state. */
@@ -335,10 +350,24 @@ dg2_status dg2_batch_refresh(dg2_batch *b);
 dg2_status dg2_batch_set_launch(dg2_batch *b, int32_t rows_per_wave, int32_t waves_per_block,
                                 int32_t graph_steps);
 
-/* Time candidate rows-per-wavefront on the members' current states (restored
- * afterwards), keep the fastest; budget_ms bounds the time spent.  The choice
- * is returned in *rows (may be NULL). */
+/* Time candidate launch shapes on the members' current states (restored
+ * afterwards) and keep the fastest: rows per wavefront x wavefronts per
+ * workgroup at the current graph length, then graph lengths 8, 16, 32 at the
+ * best shape; each candidate is timed over two graph replays.  budget_ms
+ * bounds the time spent.  With a tune cache (dg2_batch_set_tune_cache) a
+ * stored entry for the same key is taken without timing, else the choice is
+ * stored.  The chosen rows-per-wave is returned in *rows (may be NULL). */
 dg2_status dg2_batch_autotune(dg2_batch *b, double budget_ms, int32_t *rows);
+
+/* Tune cache of a batch (as dg2_set_tune_cache); the key adds the member
+ * count and the total cell count rounded up to a power of two, and an entry
+ * holds rows per wavefront, wavefronts per workgroup and the graph length. */
+dg2_status dg2_batch_set_tune_cache(dg2_batch *b, const char *path);
+
+/* Current batch launch shape and graph length, and whether the last
+ * dg2_batch_autotune took them from the cache.  Any pointer may be NULL. */
+dg2_status dg2_batch_get_launch(const dg2_batch *b, int32_t *rows, int32_t *waves, int32_t *graph_steps,
+                                int32_t *from_cache);
 
 /* Queue nsteps time steps of every member (asynchronous). */
 dg2_status dg2_batch_step(dg2_batch *b, int32_t nsteps);

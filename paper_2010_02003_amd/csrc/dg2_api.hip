@@ -18,6 +18,7 @@
 
 #include "../../include/dg2.h"
 #include "dg2_ctx.h"
+#include "dg2_tune_cache.h"
 #include "dg2_internal.h"
 
 using namespace dg2;
@@ -232,6 +233,18 @@ dg2_status reset_time(dg2_ctx *c, double t) {
   return DG2_OK;
 }
 
+}  // namespace
+
+namespace {
+// Cache key of a context's step: architecture, precision, variant, flux,
+// kernel form (fused step or per-stage kernels) and size class.
+std::string tune_key(const dg2_ctx *c) {
+  char b[256];
+  std::snprintf(b, sizeof(b), "%s|%s|%s|%s|%s|%lldx%lld", device_arch().c_str(), c->f32 ? "fp32" : "fp64",
+                c->cfg.variant == DG2_LL ? "LL" : "NL", c->cfg.flux == DG2_FLUX_ROE ? "ROE" : "HLL",
+                fused_active(c) ? "fused" : "stages", size_class(c->cfg.nx), size_class(c->cfg.ny));
+  return b;
+}
 }  // namespace
 
 extern "C" {
@@ -810,9 +823,38 @@ dg2_status dg2_set_launch(dg2_ctx *c, int32_t rows, int32_t wpb) {
   return DG2_OK;
 }
 
+dg2_status dg2_set_tune_cache(dg2_ctx *c, const char *path) {
+  if (!c) return DG2_EINVAL;
+  c->tune_path = path ? path : "";
+  return DG2_OK;
+}
+
+dg2_status dg2_get_launch(const dg2_ctx *c, int32_t *rows, int32_t *waves, int32_t *from_cache) {
+  if (!c) return DG2_EINVAL;
+  const Launch L = launch_of(c);
+  if (rows) *rows = L.R;
+  if (waves) *waves = L.wpb;
+  if (from_cache) *from_cache = c->tuned_from_cache;
+  return DG2_OK;
+}
+
 dg2_status dg2_autotune(dg2_ctx *c, double budget_ms, int32_t *rows) {
   if (!c) return DG2_EINVAL;
   if (!(budget_ms > 0)) return fail(c, DG2_EINVAL, "budget must be > 0");
+  c->tuned_from_cache = 0;
+  const std::string key = tune_key(c);
+  if (!c->tune_path.empty()) {
+    const auto m = read_tune_cache(c->tune_path);
+    const auto it = m.find(key);
+    if (it != m.end() && it->second.rows >= 1 &&
+        (it->second.waves == 1 || it->second.waves == 2 || it->second.waves == 4)) {
+      c->R_user = it->second.rows;
+      c->wpb_user = it->second.waves;
+      c->tuned_from_cache = 1;
+      if (rows) *rows = launch_of(c).R;
+      return DG2_OK;
+    }
+  }
   const size_t bytes = 9 * (size_t)c->P * c->esz;
   void *save = nullptr;
   HIPCHK(c, hipMalloc(&save, bytes), "autotune");
@@ -823,13 +865,21 @@ dg2_status dg2_autotune(dg2_ctx *c, double budget_ms, int32_t *rows) {
     return s;
   }
   const Ctrl keep = *c->hctrl;
-  const int cand[] = {2, 4, 8, 16, 32, 64, 128};
-  double best = 1e300;
-  int bestR = launch_of(c).R;
-  double spent = 0;
-  for (int R : cand) {
-    if (R > c->cfg.ny) continue;
-    c->R_user = R;
+  const int keepR = c->R_user, keepW = c->wpb_user;
+  // candidates: the built-in shape first, then rows per wavefront x
+  // wavefronts per workgroup, while the time budget lasts
+  std::vector<std::pair<int, int>> cand;
+  c->R_user = 0;
+  c->wpb_user = 4;
+  cand.push_back({launch_of(c).R, 4});
+  for (int W : {4, 2, 1})
+    for (int R : {4, 8, 16, 24, 32, 48, 64, 96})
+      if (R <= c->cfg.ny && !(R == cand[0].first && W == 4)) cand.push_back({R, W});
+  double best = 1e300, spent = 0;
+  int bestR = cand[0].first, bestW = 4;
+  for (const auto &rw : cand) {
+    c->R_user = rw.first;
+    c->wpb_user = rw.second;
     double ms = 0;
     s = dg2_time_kernels(c, 3, nullptr, nullptr, &ms);
     HIPCHK(c, hipMemcpyAsync(c->U, save, bytes, hipMemcpyDeviceToDevice, c->stream), "autotune");
@@ -839,15 +889,30 @@ dg2_status dg2_autotune(dg2_ctx *c, double budget_ms, int32_t *rows) {
     if (s != DG2_OK) break;
     if (ms < best) {
       best = ms;
-      bestR = R;
+      bestR = rw.first;
+      bestW = rw.second;
     }
     spent += 4 * ms;
     if (spent > budget_ms) break;
   }
   (void)hipFree(save);
+  if (s != DG2_OK) {
+    c->R_user = keepR;
+    c->wpb_user = keepW;
+    return s;
+  }
   c->R_user = bestR;
+  c->wpb_user = bestW;
   if (rows) *rows = bestR;
-  return s;
+  if (!c->tune_path.empty()) {
+    TuneEntry e;
+    e.rows = bestR;
+    e.waves = bestW;
+    e.ms = best;
+    if (!write_tune_cache(c->tune_path, key, e))
+      return fail(c, DG2_EINVAL, "cannot write the tune cache " + c->tune_path);
+  }
+  return DG2_OK;
 }
 
 dg2_status dg2_state_layout(const dg2_ctx *c, size_t *bytes, size_t *stride) {
@@ -884,6 +949,8 @@ struct BatchItem {
 
 struct dg2_batch {
   std::vector<dg2_ctx *> m;
+  std::string tune_path;  // dg2_batch_set_tune_cache (empty: none)
+  int tuned_from_cache = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int f32 = 0, variant = 0;
@@ -1278,10 +1345,50 @@ dg2_status dg2_batch_time_steps(dg2_batch *b, int32_t nsteps, double *ms) {
   return dg2_batch_sync(b);
 }
 
+dg2_status dg2_batch_set_tune_cache(dg2_batch *b, const char *path) {
+  if (!b) return DG2_EINVAL;
+  b->tune_path = path ? path : "";
+  return DG2_OK;
+}
+
+dg2_status dg2_batch_get_launch(const dg2_batch *b, int32_t *rows, int32_t *waves, int32_t *graph_steps,
+                                int32_t *from_cache) {
+  if (!b) return DG2_EINVAL;
+  if (rows) *rows = batch_rows(b);
+  if (waves) *waves = b->wpb;
+  if (graph_steps) *graph_steps = b->graph_steps;
+  if (from_cache) *from_cache = b->tuned_from_cache;
+  return DG2_OK;
+}
+
 dg2_status dg2_batch_autotune(dg2_batch *b, double budget_ms, int32_t *rows) {
   if (!b) return DG2_EINVAL;
   if (!(budget_ms > 0)) return bfail(b, DG2_EINVAL, "budget must be > 0");
   BCHK(b, hipStreamSynchronize(b->stream), "sync");
+  b->tuned_from_cache = 0;
+  long long cells = 0;
+  for (auto *c : b->m) cells += c->ncell;
+  const dg2_ctx *c0 = b->m[0];
+  char kb[256];
+  std::snprintf(kb, sizeof(kb), "%s|batch|%s|%s|%s|%s|%zu members|%lld cells", device_arch().c_str(),
+                b->f32 ? "fp32" : "fp64", b->variant == DG2_LL ? "LL" : "NL",
+                c0->cfg.flux == DG2_FLUX_ROE ? "ROE" : "HLL", b->fused ? "fused" : "stages", b->m.size(),
+                size_class(cells));
+  const std::string key = kb;
+  if (!b->tune_path.empty()) {
+    const auto m = read_tune_cache(b->tune_path);
+    const auto it = m.find(key);
+    if (it != m.end() && it->second.rows >= 1 && it->second.graph_steps >= 1 &&
+        (it->second.waves == 1 || it->second.waves == 2 || it->second.waves == 4)) {
+      b->R_user = it->second.rows;
+      b->wpb = it->second.waves;
+      b->graph_steps = it->second.graph_steps;
+      b->tuned_from_cache = 1;
+      dg2_status st = batch_setup(b);
+      if (rows) *rows = batch_rows(b);
+      return st;
+    }
+  }
   // save every member's state and control block
   size_t total = 0;
   for (auto *c : b->m) total += 9 * (size_t)c->P * c->esz;
@@ -1310,35 +1417,68 @@ dg2_status dg2_batch_autotune(dg2_batch *b, double budget_ms, int32_t *rows) {
     (void)hipFree(save);
     return bhip(b, e, "autotune save");
   }
-  const int keep_user = b->R_user;
-  const int cand[] = {4, 8, 12, 16, 24, 32};
+  const int keepR = b->R_user, keepW = b->wpb, keepG = b->graph_steps;
   double best = 1e300, spent = 0;
-  int bestR = batch_rows(b);
+  int bestR = batch_rows(b), bestW = b->wpb, bestG = b->graph_steps;
   dg2_status st = DG2_OK;
-  for (int R : cand) {
+  // time one candidate over two graph replays, then restore the members
+  auto trial = [&](int R, int W, int G) -> dg2_status {
     b->R_user = R;
-    if ((st = batch_setup(b)) != DG2_OK) break;
+    b->wpb = W;
+    b->graph_steps = G;
+    dg2_status s2 = batch_setup(b);
+    if (s2 != DG2_OK) return s2;
     double ms = 0;
-    st = dg2_batch_time_steps(b, 4, &ms);
+    s2 = dg2_batch_time_steps(b, 2 * G, &ms);
     e = copy_all(false);
-    if (st != DG2_OK) break;
-    if (e != hipSuccess) {
-      st = bhip(b, e, "autotune restore");
-      break;
-    }
+    if (s2 != DG2_OK) return s2;
+    if (e != hipSuccess) return bhip(b, e, "autotune restore");
     if (ms < best) {
       best = ms;
       bestR = R;
+      bestW = W;
+      bestG = G;
     }
-    spent += 5 * ms;
-    if (spent > budget_ms) break;
+    spent += (2 * G + 1) * ms;
+    return DG2_OK;
+  };
+  // rows per wavefront x wavefronts per workgroup at the current graph
+  // length, then the graph length at the best shape, while the budget lasts
+  for (int W : {4, 2, 1}) {
+    for (int R : {4, 8, 12, 16, 24, 32}) {
+      if (spent > budget_ms || st != DG2_OK) break;
+      st = trial(R, W, keepG);
+    }
+  }
+  const int R1 = bestR, W1 = bestW;
+  for (int G : {8, 16, 32}) {
+    if (spent > budget_ms || st != DG2_OK) break;
+    if (G != keepG) st = trial(R1, W1, G);
   }
   (void)hipFree(save);
-  b->R_user = st == DG2_OK ? bestR : keep_user;
-  dg2_status st2 = batch_setup(b);
+  if (st != DG2_OK) {
+    b->R_user = keepR;
+    b->wpb = keepW;
+    b->graph_steps = keepG;
+    (void)batch_setup(b);
+    return st;
+  }
+  b->R_user = bestR;
+  b->wpb = bestW;
+  b->graph_steps = bestG;
+  st = batch_setup(b);
   if (st != DG2_OK) return st;
   if (rows) *rows = bestR;
-  return st2;
+  if (!b->tune_path.empty()) {
+    TuneEntry te;
+    te.rows = bestR;
+    te.waves = bestW;
+    te.graph_steps = bestG;
+    te.ms = best;
+    if (!write_tune_cache(b->tune_path, key, te))
+      return bfail(b, DG2_EINVAL, "cannot write the tune cache " + b->tune_path);
+  }
+  return DG2_OK;
 }
 
 }  // extern "C"

@@ -58,6 +58,10 @@ struct dg2_ctx {
   double *diag_part = nullptr, *diag_out = nullptr;
   // launch shape
   int R_user = 0, wpb_user = 4;
+  // autotuner cache file (dg2_set_tune_cache; empty: none) and whether the
+  // current launch shape came from it
+  std::string tune_path;
+  int tuned_from_cache = 0;
   std::string err;
 };
 

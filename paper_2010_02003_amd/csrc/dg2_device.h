@@ -126,10 +126,14 @@ template <typename real>
 __device__ __forceinline__ void dummy_limit(real h, real qx, real qy, real tol, real &hs, real &u,
                                             real &v) {
   hs = h > real(0) ? h : real(0);
-  // one select on the reciprocal zeroes both velocities of a dry limit
-  const real r = h > tol ? drcp(h) : real(0);
-  u = qx * r;
-  v = qy * r;
+  if (h > tol) {
+    const real r = drcp(h);
+    u = qx * r;
+    v = qy * r;
+  } else {
+    u = real(0);
+    v = real(0);
+  }
 }
 
 // HLL flux through a face with normal velocity u and tangential velocity v.
@@ -257,13 +261,18 @@ __device__ __forceinline__ void flux_x(real h, real qx, real qy, real g, real to
                                        real &F1, real &F2) {
   const real hp = h > real(0) ? h : real(0);
   const real pres = real(0.5) * g * hp * hp;
-  // a dry point has zero velocities: zeroing the reciprocal zeroes u, v, q
-  const real r = h > tol ? drcp(h) : real(0);
-  const real u = qx * r, v = qy * r;
-  const real q = hp * u;
-  F0 = q;
-  F1 = q * u + pres;
-  F2 = q * v;
+  if (h > tol) {
+    const real r = drcp(h);
+    const real u = qx * r, v = qy * r;
+    const real q = hp * u;
+    F0 = q;
+    F1 = q * u + pres;
+    F2 = q * v;
+  } else {
+    F0 = real(0);
+    F1 = pres;
+    F2 = real(0);
+  }
 }
 
 // Physical y-flux at a point, returned as [mass, x-momentum, y-momentum].
@@ -272,12 +281,18 @@ __device__ __forceinline__ void flux_y(real h, real qx, real qy, real g, real to
                                        real &G1, real &G2) {
   const real hp = h > real(0) ? h : real(0);
   const real pres = real(0.5) * g * hp * hp;
-  const real r = h > tol ? drcp(h) : real(0);
-  const real u = qx * r, v = qy * r;
-  const real q = hp * v;
-  G0 = q;
-  G1 = q * u;
-  G2 = q * v + pres;
+  if (h > tol) {
+    const real r = drcp(h);
+    const real u = qx * r, v = qy * r;
+    const real q = hp * v;
+    G0 = q;
+    G1 = q * u;
+    G2 = q * v + pres;
+  } else {
+    G0 = real(0);
+    G1 = real(0);
+    G2 = pres;
+  }
 }
 
 // Implicit friction increment at one point.  The split friction ODE

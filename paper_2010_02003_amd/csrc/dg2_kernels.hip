@@ -77,31 +77,31 @@ __device__ __forceinline__ void cell_operator(const Row<real> &cur, real FE0, re
                                               real GN2, real GS0, real GS1, real GS2, real zbx,
                                               real zby, real g, real tol, real idx, real idy,
                                               real *Lop) {
-  // Gauss-point values of the dummy modes, U0 +- U1/sqrt(3) with U0 = (E + W)/2
-  // and U1 = (E - W)/2, as c1 E + c2 W and c2 E + c1 W
-  const real c1 = real(0.5 + 0.5 * kInvSqrt3), c2 = real(0.5 - 0.5 * kInvSqrt3);
+  const real half = real(0.5), is3 = real(kInvSqrt3), two_g = real(2) * g;
+  const real tg3 = real(2) * g / real(3);
   const real e1 = cur.eh * cur.eu, e2 = cur.eh * cur.ev;
   const real w1 = cur.wh * cur.wu, w2 = cur.wh * cur.wv;
+  const real A0 = half * (cur.eh + cur.wh), A1 = half * (e1 + w1), A2 = half * (e2 + w2);
+  const real B0 = half * (cur.eh - cur.wh), B1 = half * (e1 - w1), B2 = half * (e2 - w2);
   const real n1 = cur.nh * cur.nu, n2 = cur.nh * cur.nv;
   const real s1 = cur.sh * cur.su, s2 = cur.sh * cur.sv;
+  const real C0 = half * (cur.nh + cur.sh), C1 = half * (n1 + s1), C2 = half * (n2 + s2);
+  const real D0 = half * (cur.nh - cur.sh), D1 = half * (n1 - s1), D2 = half * (n2 - s2);
   real Fp0, Fp1, Fp2, Fm0, Fm1, Fm2, Gp0, Gp1, Gp2, Gm0, Gm1, Gm2;
-  flux_x(c1 * cur.eh + c2 * cur.wh, c1 * e1 + c2 * w1, c1 * e2 + c2 * w2, g, tol, Fp0, Fp1, Fp2);
-  flux_x(c2 * cur.eh + c1 * cur.wh, c2 * e1 + c1 * w1, c2 * e2 + c1 * w2, g, tol, Fm0, Fm1, Fm2);
-  flux_y(c1 * cur.nh + c2 * cur.sh, c1 * n1 + c2 * s1, c1 * n2 + c2 * s2, g, tol, Gp0, Gp1, Gp2);
-  flux_y(c2 * cur.nh + c1 * cur.sh, c2 * n1 + c1 * s1, c2 * n2 + c1 * s2, g, tol, Gm0, Gm1, Gm2);
-  // bed terms: 2 g h0 z1 / dx with h0 = (E + W)/2, and (2g/3) h1 z1 with h1 = (E - W)/2
-  const real gx = g * zbx * idx, gy = g * zby * idy;
-  const real g3x = g * zbx * real(1.0 / 3.0), g3y = g * zby * real(1.0 / 3.0);
+  flux_x(A0 + B0 * is3, A1 + B1 * is3, A2 + B2 * is3, g, tol, Fp0, Fp1, Fp2);
+  flux_x(A0 - B0 * is3, A1 - B1 * is3, A2 - B2 * is3, g, tol, Fm0, Fm1, Fm2);
+  flux_y(C0 + D0 * is3, C1 + D1 * is3, C2 + D2 * is3, g, tol, Gp0, Gp1, Gp2);
+  flux_y(C0 - D0 * is3, C1 - D1 * is3, C2 - D2 * is3, g, tol, Gm0, Gm1, Gm2);
   const real m3x = real(-3) * idx, m3y = real(-3) * idy;
   Lop[0] = -(FE0 - FW0) * idx - (GN0 - GS0) * idy;
-  Lop[3] = -(FE1 - FW1) * idx - (GN1 - GS1) * idy - gx * (cur.eh + cur.wh);
-  Lop[6] = -(FE2 - FW2) * idx - (GN2 - GS2) * idy - gy * (cur.nh + cur.sh);
+  Lop[3] = -(FE1 - FW1) * idx - (GN1 - GS1) * idy - two_g * A0 * zbx * idx;
+  Lop[6] = -(FE2 - FW2) * idx - (GN2 - GS2) * idy - two_g * C0 * zby * idy;
   Lop[1] = m3x * ((FE0 + FW0) - (Fp0 + Fm0));
-  Lop[4] = m3x * ((FE1 + FW1) - (Fp1 + Fm1) + g3x * (cur.eh - cur.wh));
+  Lop[4] = m3x * ((FE1 + FW1) - (Fp1 + Fm1) + tg3 * B0 * zbx);
   Lop[7] = m3x * ((FE2 + FW2) - (Fp2 + Fm2));
   Lop[2] = m3y * ((GN0 + GS0) - (Gp0 + Gm0));
   Lop[5] = m3y * ((GN1 + GS1) - (Gp1 + Gm1));
-  Lop[8] = m3y * ((GN2 + GS2) - (Gp2 + Gm2) + g3y * (cur.nh - cur.sh));
+  Lop[8] = m3y * ((GN2 + GS2) - (Gp2 + Gm2) + tg3 * D0 * zby);
 }
 
 // One side's boundary segment as a lane sees it: kind (kBc*), whether this
@@ -291,13 +291,12 @@ __device__ __forceinline__ void load_raw(const Scen<real> &s, const real *src, i
 
 // Stage input of one row from its raw planes: mirror ghosts, then in stage 1
 // rain and the friction split, then the dummy face limits.
-// YM = false: the row is known to lie inside the grid (no ghost row).
-template <typename real, int STAGE, bool YM = true>
+template <typename real, int STAGE>
 __device__ __forceinline__ void build_row(const Raw<real, STAGE> &raw, int r, int ny, bool mx,
                                           real rain, real gdt, real tol, Row<real> &row) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) row.W[k] = raw.W[k];
-  mirror(row.W, mx, YM && ((r < 0) || (r >= ny)));
+  mirror(row.W, mx, (r < 0) || (r >= ny));
   if (STAGE == 1) {
     row.W[0] += rain;
     apply_friction(row.W, gdt * raw.n * raw.n, tol);
@@ -643,8 +642,7 @@ __device__ __forceinline__ bool fused_yin(const Scen<real> &s, int seg, int R) {
 // without them (an interior tile) the march runs two rows per iteration.
 // Dropping a boundary treatment a tile does not need leaves the march fewer
 // live scalars and branches (same arithmetic, bitwise equal results).
-// FL: the partly-wet rule off (0), on (1), or as the launch's Consts say (2).
-template <typename real, int FLUX, bool down, bool CHECK, bool XE, bool YE, int FL>
+template <typename real, int FLUX, bool down, bool CHECK, bool XE, bool YE>
 __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Consts &c, int strip,
                                                 int seg, int R, int lane) {
   if (CHECK && s.ctrl->aux == 0u) return;
@@ -664,7 +662,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
   }
 
   const real dt = (real)dtd, g = (real)c.g, tol = (real)c.tol;
-  const bool flat = FL == 2 ? c.flat != 0 : FL == 1;
+  const bool flat = c.flat != 0;
   const real half = real(0.5);
   const int ny = s.ny;
   const int i = strip * kStripF + lane - 2;
@@ -720,9 +718,9 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
       Row<real> back;
       load_raw<real, 1>(s, src, afirst - d, ci, K[0].raw);
       load_raw<real, 1>(s, src, afirst, ci, K[1].raw);
-      build_row<real, 1, YE>(K[0].raw, afirst - d, ny, mx, rain, gdt, tol, back);
+      build_row<real, 1>(K[0].raw, afirst - d, ny, mx, rain, gdt, tol, back);
       load_raw<real, 1>(s, src, afirst + d, ci, K[0].raw);
-      build_row<real, 1, YE>(K[1].raw, afirst, ny, mx, rain, gdt, tol, K[0].A);
+      build_row<real, 1>(K[1].raw, afirst, ny, mx, rain, gdt, tol, K[0].A);
       face_behind<FLUX, down>(s, afirst, i, back, K[0].A, colS1, colN1, qS1, qN1, g, tol, K[0].CA[0],
                               K[0].CA[1], K[0].CA[2], K[0].CA[3]);
     }
@@ -737,7 +735,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
       const real zx = ld_at(s.z + s.P, offA), zy = ld_at(s.z + 2 * s.P, offA);
 
       // ---- stage 1 on row r ----
-      build_row<real, 1, YE>(kc.raw, r + d, ny, mx, rain, gdt, tol, kn.A);
+      build_row<real, 1>(kc.raw, r + d, ny, mx, rain, gdt, tol, kn.A);
       face_ahead<FLUX, down>(s, r, i, kc.A, kn.A, colS1, colN1, qS1, qN1, g, tol, kn.CA[0], kn.CA[1],
                              kn.CA[2], kn.CA[3]);
       real u1[9];
@@ -782,7 +780,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
         Raw<real, 2> rb;
 #pragma unroll
         for (int k = 0; k < 9; ++k) rb.W[k] = u1[k];
-        build_row<real, 2, YE>(rb, r, ny, mx, rain, gdt, tol, kn.B);
+        build_row<real, 2>(rb, r, ny, mx, rain, gdt, tol, kn.B);
       }
       if (r == afirst) {
         if (YE && afirst == jfirst) {
@@ -843,9 +841,9 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
       Row<real> back;
       load_raw<real, 1>(s, src, afirst - d, ci, rawA);
       load_raw<real, 1>(s, src, afirst, ci, rawN);
-      build_row<real, 1, YE>(rawA, afirst - d, ny, mx, rain, gdt, tol, back);
+      build_row<real, 1>(rawA, afirst - d, ny, mx, rain, gdt, tol, back);
       load_raw<real, 1>(s, src, afirst + d, ci, rawA);
-      build_row<real, 1, YE>(rawN, afirst, ny, mx, rain, gdt, tol, curA);
+      build_row<real, 1>(rawN, afirst, ny, mx, rain, gdt, tol, curA);
       face_behind<FLUX, down>(s, afirst, i, back, curA, colS1, colN1, qS1, qN1, g, tol, CA0, CA1, CA2,
                               dCA);
     }
@@ -864,7 +862,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
 
       // ---- stage 1 on row r ----
       Row<real> nxtA;
-      build_row<real, 1, YE>(rawA, r + d, ny, mx, rain, gdt, tol, nxtA);
+      build_row<real, 1>(rawA, r + d, ny, mx, rain, gdt, tol, nxtA);
       real FA0, FA1, FA2, dFA;
       face_ahead<FLUX, down>(s, r, i, curA, nxtA, colS1, colN1, qS1, qN1, g, tol, FA0, FA1, FA2, dFA);
       real u1[9];
@@ -909,7 +907,7 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
         Raw<real, 2> rb;
 #pragma unroll
         for (int k = 0; k < 9; ++k) rb.W[k] = u1[k];
-        build_row<real, 2, YE>(rb, r, ny, mx, rain, gdt, tol, nxtB);
+        build_row<real, 2>(rb, r, ny, mx, rain, gdt, tol, nxtB);
       }
       if (r == afirst) {
         if (YE && afirst == jfirst) {
@@ -1007,31 +1005,29 @@ __device__ __forceinline__ void march_fused_dir(const Scen<real> &s, const Const
 
 // One tile of the fused march: the instantiation without the boundary
 // treatment a tile does not need (west/east edge, south/north edge).
-template <typename real, int FLUX, bool down, bool CHECK, int FL>
+template <typename real, int FLUX, bool down, bool CHECK>
 __device__ __forceinline__ void fused_tile(const Scen<real> &s, const Consts &c, int strip, int seg,
                                            int R, int lane) {
   const bool xin = fused_xin(s, strip), yin = fused_yin(s, seg, R);
   if (xin && yin)
-    march_fused_dir<real, FLUX, down, CHECK, false, false, FL>(s, c, strip, seg, R, lane);
+    march_fused_dir<real, FLUX, down, CHECK, false, false>(s, c, strip, seg, R, lane);
   else if (yin)
-    march_fused_dir<real, FLUX, down, CHECK, true, false, FL>(s, c, strip, seg, R, lane);
+    march_fused_dir<real, FLUX, down, CHECK, true, false>(s, c, strip, seg, R, lane);
   else if (xin)
-    march_fused_dir<real, FLUX, down, CHECK, false, true, FL>(s, c, strip, seg, R, lane);
+    march_fused_dir<real, FLUX, down, CHECK, false, true>(s, c, strip, seg, R, lane);
   else
-    march_fused_dir<real, FLUX, down, CHECK, true, true, FL>(s, c, strip, seg, R, lane);
+    march_fused_dir<real, FLUX, down, CHECK, true, true>(s, c, strip, seg, R, lane);
 }
 
-// The partly-wet rule is a template parameter here (FL 0 or 1), so the
-// default kernel carries none of its arithmetic.
-template <typename real, int FLUX, bool CHECK, int FL>
+template <typename real, int FLUX, bool CHECK>
 __global__ void __launch_bounds__(256, 3) k_step_nl(Scen<real> s, Consts c, Launch L) {
   int item;
   if (!stage_item<2>(L, item)) return;
   const int strip = item % L.nstrips, seg = item / L.nstrips;
   if (seg & 1)
-    fused_tile<real, FLUX, true, CHECK, FL>(s, c, strip, seg, L.R, threadIdx.x & 63);
+    fused_tile<real, FLUX, true, CHECK>(s, c, strip, seg, L.R, threadIdx.x & 63);
   else
-    fused_tile<real, FLUX, false, CHECK, FL>(s, c, strip, seg, L.R, threadIdx.x & 63);
+    fused_tile<real, FLUX, false, CHECK>(s, c, strip, seg, L.R, threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------------------
@@ -1352,14 +1348,14 @@ __global__ void __launch_bounds__(256, 3) k_batch_step(const Scen<real> *__restr
     const bool in = fused_xin(s, strip) && fused_yin(s, seg, R);
     if (seg & 1) {
       if (in)
-        march_fused_dir<real, FLUX, true, false, false, false, 2>(s, c, strip, seg, R, lane);
+        march_fused_dir<real, FLUX, true, false, false, false>(s, c, strip, seg, R, lane);
       else
-        march_fused_dir<real, FLUX, true, false, true, true, 2>(s, c, strip, seg, R, lane);
+        march_fused_dir<real, FLUX, true, false, true, true>(s, c, strip, seg, R, lane);
     } else {
       if (in)
-        march_fused_dir<real, FLUX, false, false, false, false, 2>(s, c, strip, seg, R, lane);
+        march_fused_dir<real, FLUX, false, false, false, false>(s, c, strip, seg, R, lane);
       else
-        march_fused_dir<real, FLUX, false, false, true, true, 2>(s, c, strip, seg, R, lane);
+        march_fused_dir<real, FLUX, false, false, true, true>(s, c, strip, seg, R, lane);
     }
   }
 }
@@ -1641,25 +1637,17 @@ hipError_t launch_fused(const Scen<real> &s, const Consts &c, const Launch &L, h
                         bool check) {
   const dim3 block(64 * L.wpb);
   const dim3 grid((L.nitems + L.wpb - 1) / L.wpb);
-#define DG2_STEP_NL(FLUX, CHECK)                                                                   \
-  do {                                                                                              \
-    if (c.flat)                                                                                     \
-      hipLaunchKernelGGL((k_step_nl<real, FLUX, CHECK, 1>), grid, block, 0, st, s, c, L);           \
-    else                                                                                            \
-      hipLaunchKernelGGL((k_step_nl<real, FLUX, CHECK, 0>), grid, block, 0, st, s, c, L);           \
-  } while (0)
   if (c.flux == kFluxRoe) {
     if (check)
-      DG2_STEP_NL(kFluxRoe, true);
+      hipLaunchKernelGGL((k_step_nl<real, kFluxRoe, true>), grid, block, 0, st, s, c, L);
     else
-      DG2_STEP_NL(kFluxRoe, false);
+      hipLaunchKernelGGL((k_step_nl<real, kFluxRoe, false>), grid, block, 0, st, s, c, L);
   } else {
     if (check)
-      DG2_STEP_NL(kFluxHLL, true);
+      hipLaunchKernelGGL((k_step_nl<real, kFluxHLL, true>), grid, block, 0, st, s, c, L);
     else
-      DG2_STEP_NL(kFluxHLL, false);
+      hipLaunchKernelGGL((k_step_nl<real, kFluxHLL, false>), grid, block, 0, st, s, c, L);
   }
-#undef DG2_STEP_NL
   return hipGetLastError();
 }
 

@@ -83,6 +83,11 @@ _SIGS = {
     "dg2_set_stage_check": (c_int32, [c_void_p, c_int32]),
     "dg2_set_partly_wet_flat": (c_int32, [c_void_p, c_int32]),
     "dg2_autotune": (c_int32, [c_void_p, c_double, POINTER(c_int32)]),
+    "dg2_set_tune_cache": (c_int32, [c_void_p, ctypes.c_char_p]),
+    "dg2_get_launch": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]),
+    "dg2_batch_set_tune_cache": (c_int32, [c_void_p, ctypes.c_char_p]),
+    "dg2_batch_get_launch": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
+                                       POINTER(c_int32)]),
     "dg2_state_layout": (c_int32, [c_void_p, POINTER(c_size_t), POINTER(c_size_t)]),
     "dg2_bind_device_state": (c_int32, [c_void_p, c_void_p, c_size_t]),
     "dg2_batch_create": (c_int32, [POINTER(c_void_p), c_int32, c_void_p, POINTER(c_void_p)]),
@@ -268,6 +273,15 @@ class Sim:
         self._check(self._lib.dg2_autotune(self._ctx, budget_ms, byref(r)))
         return r.value
 
+    def set_tune_cache(self, path: Optional[str]):
+        self._check(self._lib.dg2_set_tune_cache(self._ctx, path.encode() if path else None))
+
+    def get_launch(self):
+        """(rows per wavefront, wavefronts per workgroup, taken from the tune cache)."""
+        r, w, f = c_int32(), c_int32(), c_int32()
+        self._check(self._lib.dg2_get_launch(self._ctx, byref(r), byref(w), byref(f)))
+        return r.value, w.value, bool(f.value)
+
     # -- run -------------------------------------------------------------------
     def step(self, nsteps: int = 1):
         self._check(self._lib.dg2_step(self._ctx, nsteps))
@@ -385,6 +399,15 @@ class Batch:
         r = c_int32()
         self._check(self._lib.dg2_batch_autotune(self._b, budget_ms, byref(r)))
         return r.value
+
+    def set_tune_cache(self, path: Optional[str]):
+        self._check(self._lib.dg2_batch_set_tune_cache(self._b, path.encode() if path else None))
+
+    def get_launch(self):
+        """(rows per wavefront, wavefronts per workgroup, graph length, taken from the tune cache)."""
+        r, w, g, f = c_int32(), c_int32(), c_int32(), c_int32()
+        self._check(self._lib.dg2_batch_get_launch(self._b, byref(r), byref(w), byref(g), byref(f)))
+        return r.value, w.value, g.value, bool(f.value)
 
     def step(self, nsteps: int = 1):
         self._check(self._lib.dg2_batch_step(self._b, nsteps))
