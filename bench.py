@@ -339,6 +339,7 @@ def main():
     traffic = None
     valu_busy = None
     valu_insts = None
+    copy_gbs = None
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     sname = "k_stage_ll" if sc.variant == "LL" else "k_stage_nl"
     kname = "k_step_nl" if fused else sname
@@ -348,12 +349,18 @@ def main():
             traffic = ent.get("bytes_per_launch")
             valu_busy = ent.get("valu_busy")
             valu_insts = ent.get("valu_insts_per_launch")
+            copy_gbs = ent.get("copy_bandwidth_gbs")
     real = "float" if esz == 4 else "double"
     if fused:
         ach = cells * bf / (ms1 * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": "fused step (k_step_nl<%s, HLL>)" % real,
                 "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": traffic, "bytes_per_cell": bf, "ms_per_launch": ms1,
+                "traffic": traffic, "bytes_per_cell": bf,
+                "basis": "algorithmic bytes of one fused launch: per cell the 9 state planes, 2 bed "
+                         "slopes and the Manning plane read once and the 9 new planes written once",
+                "ms_per_launch": ms1,
+                # the plain device-copy bandwidth measured on this machine with the counters
+                "copy_ceiling": None if copy_gbs is None else {"GB/s": copy_gbs, "frac": ach / copy_gbs},
                 "step_frac": cells * bf / (wall / args.steps) / 1e9 / HBM_PEAK_GBS,
                 "ms_per_step_with_events": ms_step_ev,
                 # the kernel is bound by vector-ALU issue, not HBM: the VALUBusy
