@@ -304,8 +304,12 @@ def main():
     # belongs to the wet steady state.
     if args.spinup_s > 0:
         sim.set_step_kernel(False)
-        sim.run_to(args.spinup_s)
-        sim.sync()
+        t_mark = 0.0
+        while t_mark < args.spinup_s:
+            t_mark = min(args.spinup_s, t_mark + 5.0)
+            sim.run_to(t_mark)
+            sim.sync()
+            print("spin-up: t = %.1f s, %d steps" % (t_mark, sim.time()[1]), file=sys.stderr, flush=True)
         sim.set_step_kernel(args.step_kernel == "fused")
     if args.warmup > 0:
         sim.step(args.warmup)

@@ -65,8 +65,8 @@ struct PlanArgs {
 // fix-up steps cost a third of the FP64 stage kernels' time): the
 // reciprocal takes two Newton steps on the estimate of v_rcp_f64, a quotient
 // one correction of a * (1/b), the square root one Newton step on the
-// estimate of v_sqrt_f64; each result is within an ulp or two of the
-// correctly rounded one.  rcbrt stays the library's.
+// estimate of v_sqrt_f64, h^(-1/3) two Newton steps on an FP32 estimate;
+// each result is within an ulp or two of the correctly rounded one.
 template <typename real> __device__ __forceinline__ real dsqrt(real x);
 template <> __device__ __forceinline__ double dsqrt<double>(double x) {
   // y + (x - y^2) / (2 y) on the hardware estimate y
@@ -94,8 +94,23 @@ template <> __device__ __forceinline__ double ddiv<double>(double a, double b) {
 template <> __device__ __forceinline__ float ddiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 // h^(-7/3) for a depth h above the drying tolerance
 template <typename real> __device__ __forceinline__ real pow_m7_3(real h);
+// h^(-1/3) for a depth above the drying tolerance: an FP32 estimate
+// exp2(-log2(h)/3), then two Newton steps on y^-3 = h in FP64,
+// y <- y + y (1 - h y^3) / 3 (the error squares at each step: ~1e-7, ~1e-14,
+// then rounding).  Depths below 1e-30 (not expected: tol_dry is far above)
+// take the library's rcbrt.
+__device__ __forceinline__ double rcbrt_pos(double h) {
+  if (__builtin_expect(h < 1e-30, 0)) return rcbrt(h);
+  double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)h) * (-1.0f / 3.0f));
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double e = __builtin_fma(-h, y * y * y, 1.0);
+    y = __builtin_fma(y * (1.0 / 3.0), e, y);
+  }
+  return y;
+}
 template <> __device__ __forceinline__ double pow_m7_3<double>(double h) {
-  const double rc = rcbrt(h), rc2 = rc * rc;
+  const double rc = rcbrt_pos(h), rc2 = rc * rc;
   return (rc2 * rc2) * (rc2 * rc);
 }
 template <> __device__ __forceinline__ float pow_m7_3<float>(float h) {
@@ -155,7 +170,17 @@ __device__ __forceinline__ void hll(real hL, real uL, real vL, real hR, real uR,
   const real qL = hL * uL, qR = hR * uR;
   const real FL0 = qL, FL1 = qL * uL + real(0.5) * g * hL * hL, FL2 = qL * vL;
   const real FR0 = qR, FR1 = qR * uR + real(0.5) * g * hR * hR, FR2 = qR * vR;
-  if (sL >= real(0)) {
+  if constexpr (sizeof(real) == 8) {
+    // FP64: one formula for the three wave regimes (sl = min(sL, 0) and
+    // sr = max(sR, 0) give F_L when sL >= 0 and F_R when sR <= 0), which
+    // replaces six 64-bit selects by two min/max
+    const real sl = dmin(sL, real(0)), sr = dmax(sR, real(0));
+    const real inv = drcp(sr - sl);
+    const real ss = sl * sr;
+    F0 = (sr * FL0 - sl * FR0 + ss * (hR - hL)) * inv;
+    F1 = (sr * FL1 - sl * FR1 + ss * (qR - qL)) * inv;
+    F2 = (sr * FL2 - sl * FR2 + ss * (hR * vR - hL * vL)) * inv;
+  } else if (sL >= real(0)) {
     F0 = FL0; F1 = FL1; F2 = FL2;
   } else if (sR <= real(0)) {
     F0 = FR0; F1 = FR1; F2 = FR2;
