@@ -70,7 +70,7 @@ __host__ __device__ inline void pflux_vjp(double h, double u, double v, double g
 __host__ __device__ inline double min_vjp_a(double a, double b) { return a < b ? 1.0 : (a == b ? 0.5 : 0.0); }
 __host__ __device__ inline double max_vjp_a(double a, double b) { return a > b ? 1.0 : (a == b ? 0.5 : 0.0); }
 
-// ---- HLL flux (reading R1) and its adjoint ------------------------------------
+// ---- HLL flux (Toro wave speeds) and its adjoint -----------------------------
 __host__ __device__ inline void hll(double hL, double uL, double vL, double hR, double uR,
                                     double vR, double g, double tol, double *F) {
   const bool dryL = hL <= tol, dryR = hR <= tol;
@@ -194,7 +194,7 @@ __host__ __device__ inline void gflux_vjp(double h, double qn, double qt, double
   dummy_vjp(h, qn, qt, tol, lhs, lun, lut, lh, lqn, lqt);
 }
 
-// ---- inflow face flux (reading R12), normal components [F0, F1] -------------
+// ---- prescribed inflow face flux, normal components [F0, F1] ----------------
 __host__ __device__ inline void inflow(double q, double h_in, double g, double &F0, double &F1) {
   const double hc = cbrt(q * q / g);
   const double hb = dmax(h_in, hc);
@@ -213,7 +213,7 @@ __host__ __device__ inline void inflow_vjp(double q, double h_in, double g, doub
   if (q != 0.0) lq += max_vjp_a(hc, h_in) * lhb * (2.0 / 3.0) * hc / q;
 }
 
-// ---- friction at one point (reading R8): increment and its adjoint ----------
+// ---- implicit friction at one point: increment and its adjoint --------------
 // a = dt g n^2 |q| h^(-7/3); dq = -q a / (1 + a)
 __host__ __device__ inline void fric_point(double h, double qx, double qy, double n, double gdt,
                                            double tol, double &dx, double &dy) {
@@ -305,9 +305,10 @@ __host__ __device__ inline void fric_elem_vjp(const double *U, double n, double 
 }
 
 
-// ---- wet/dry treatment at the end of a stage (reading R15) ------------------
+// ---- wet/dry treatment at the end of a stage ---------------------------------
 // Code of the decision taken on a stage output: 1 = dry (discharge modes set
-// to zero), 2 = partly wet (every slope mode set to zero), 0 = unchanged.
+// to zero, Sec. 2.1.3), 2 = partly wet with the optional partly-wet rule on
+// (every slope mode set to zero), 0 = unchanged.
 // The adjoint of the treatment zeroes the same entries of the adjoint.
 __host__ __device__ inline void apply_mask(unsigned char m, double *v) {
   if (m & 1u) {
@@ -385,7 +386,7 @@ __host__ __device__ inline void load9(const double *base, long long P, long long
 // its four neighbours through the face fluxes and the wall-revised bed).
 // lq[side] receives the adjoint of the unit discharge of an inflow face of
 // this cell on that side (0 when there is none).  Wall ghosts are mirror
-// images of the cell (Sec. 2.1.2 reading R11), so their dependence folds
+// images of the cell (walls as mirror ghost cells), so their dependence folds
 // back onto the cell; ghosts carry no operator of their own.
 __host__ __device__ inline void operator_vjp(const OpAdj &a, int i, int j, double *JT, double *lq) {
   const long long P = a.P;

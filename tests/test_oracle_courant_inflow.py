@@ -1,6 +1,7 @@
 """Pins of two oracle parts that no other test fixes independently.
 
-Courant step (Sec. 2.1.2 gives Cr = 0.3; which speeds enter is reading R6).
+Courant step (Sec. 2.1.2 gives Cr = 0.3; which speeds enter is a reading: the
+directional minimum over wet cell means).
 The pin measures the Courant number that the chosen step realises from the
 definition of the Courant number, with the wave speeds taken a different
 way: as the spectral radius of the Jacobians dF/dU and dG/dU of the physical
@@ -11,8 +12,9 @@ largest Courant number over the wet cells must be exactly Cr, and the step
 must be dt_max when nothing is wet.  A swapped dx/dy, a missing absolute
 value on a velocity or a dry cell taken into account all fail it.
 
-Discharge inflow (reading R12: face flux [q, q^2/h_b + g h_b^2/2], h_b the
-larger of the inner dummy depth and the critical depth (q^2/g)^(1/3)).
+Discharge inflow (a reading, the paper gives no boundary treatment: face
+flux [q, q^2/h_b + g h_b^2/2], h_b the larger of the inner dummy depth and
+the critical depth (q^2/g)^(1/3)).
 A constant discharge entering a dry, flat, frictionless channel has an
 exact solution: the boundary state is critical, and the flow beyond it is
 Ritter's dam-break fan of a reservoir of depth 9/4 times the critical depth
