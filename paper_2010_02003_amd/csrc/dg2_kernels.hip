@@ -1378,6 +1378,42 @@ __device__ double hydrograph_at(int n, const double *t, const double *Q, double 
   return Q[k] * (1.0 - w) + Q[k + 1] * w;
 }
 
+// The hydrograph samples a lookup usually needs (both ends and the hinted
+// interval), loaded together up front; lookups whose time falls in the
+// hinted interval then need no further load.
+struct HydHint {
+  int n, k;
+  double t0, tn, tk, tk1, Q0, Qn, Qk, Qk1;
+};
+__device__ __forceinline__ HydHint hyd_hint(int n, const double *t, const double *Q, int k) {
+  HydHint h;
+  h.n = n;
+  h.k = k < 0 ? 0 : (k > n - 2 ? (n >= 2 ? n - 2 : 0) : k);
+  const int k1 = h.k + 1 < n ? h.k + 1 : n - 1;
+  h.t0 = t[0];
+  h.tn = t[n - 1];
+  h.tk = t[h.k];
+  h.tk1 = t[k1];
+  h.Q0 = Q[0];
+  h.Qn = Q[n - 1];
+  h.Qk = Q[h.k];
+  h.Qk1 = Q[k1];
+  return h;
+}
+// hydrograph_at with the samples of a hint; k as there.  Bitwise the same
+// value and interval: a time in [t_k, t_k+1) of a sorted table has k as its
+// interval whatever the scan starts from.
+__device__ __forceinline__ double hydrograph_hinted(const HydHint &h, const double *t,
+                                                    const double *Q, double x, int &k) {
+  if (x <= h.t0) return h.Q0;
+  if (x >= h.tn) return h.Qn;
+  if (k == h.k && h.tk <= x && x < h.tk1) {
+    const double w = (x - h.tk) / (h.tk1 - h.tk);
+    return h.Qk * (1.0 - w) + h.Qk1 * w;
+  }
+  return hydrograph_at(h.n, t, Q, x, k);
+}
+
 // The pending step from time t with size dt: its rain depth and the
 // boundary values (unit inflow or level) at the two stage times.
 __device__ void set_step(Ctrl *c, const PlanArgs &p, double dt) {
@@ -1388,9 +1424,10 @@ __device__ void set_step(Ctrl *c, const PlanArgs &p, double dt) {
   for (int sd = 0; sd < 4; ++sd) {
     if (p.nhyd[sd] > 0) {
       int k = c->hyd_k[sd];
-      c->qin[sd][0] = hydrograph_at(p.nhyd[sd], p.hyd_t[sd], p.hyd_Q[sd], t, k) / p.seg_len[sd];
+      const HydHint h = hyd_hint(p.nhyd[sd], p.hyd_t[sd], p.hyd_Q[sd], k);
+      c->qin[sd][0] = hydrograph_hinted(h, p.hyd_t[sd], p.hyd_Q[sd], t, k) / p.seg_len[sd];
       const int k0 = k;
-      c->qin[sd][1] = hydrograph_at(p.nhyd[sd], p.hyd_t[sd], p.hyd_Q[sd], t + dt, k) / p.seg_len[sd];
+      c->qin[sd][1] = hydrograph_hinted(h, p.hyd_t[sd], p.hyd_Q[sd], t + dt, k) / p.seg_len[sd];
       c->hyd_k[sd] = k0;
     } else {
       c->qin[sd][0] = 0.0;
@@ -1436,7 +1473,9 @@ __device__ void plan_step(Ctrl *c, const PlanArgs &p, int mode, double t_end, in
 
 __global__ void k_plan(Ctrl *c, PlanArgs p, int mode, double t_end, int set_tend) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  plan_step(c, p, mode, t_end, set_tend);
+  Ctrl cl = *c;
+  plan_step(&cl, p, mode, t_end, set_tend);
+  *c = cl;
 }
 
 // Stage-1 Courant check (an option; one thread).  After stage 1 (first) or a
@@ -1472,7 +1511,13 @@ __global__ void k_plan_batch(Ctrl *const *ctrls, const PlanArgs *pa, int n, int 
                              double t_end, int set_tend) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  plan_step(ctrls[k], pa[k], mode, t_end, set_tend);
+  // private copies: every load is issued at once, and the planner's stores
+  // cannot alias the arguments it reads afterwards
+  Ctrl *const cp = ctrls[k];
+  const PlanArgs p = pa[k];
+  Ctrl c = *cp;
+  plan_step(&c, p, mode, t_end, set_tend);
+  *cp = c;
 }
 
 // Courant minimum of the state s.U, into *bits (after the state was set from
