@@ -277,7 +277,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the DG2 step here runs on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md, not built); run with --gpus 1",
+              "(multi-GPU sharding is not built); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

@@ -59,7 +59,7 @@ typedef enum {
   DG2_EHIP = -3,         /* a HIP runtime call failed                    */
   DG2_ESTATE = -4,       /* call not valid in the current state          */
   DG2_ENUMERIC = -5,     /* NaN found in the state on the device         */
-  DG2_EUNSUPPORTED = -6  /* option not available in this build           */
+  DG2_EUNSUPPORTED = -6  /* option not available in this library         */
 } dg2_status;
 
 typedef enum { DG2_FP64 = 0, DG2_FP32 = 1 } dg2_prec;

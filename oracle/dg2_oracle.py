@@ -787,7 +787,7 @@ def energy(U: torch.Tensor, bed: Bed, prm: Params) -> float:
 
 
 # ---------------------------------------------------------------------------
-# Driver
+# Time stepping to a target time
 # ---------------------------------------------------------------------------
 
 @dataclass

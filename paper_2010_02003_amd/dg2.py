@@ -425,7 +425,7 @@ class Batch:
 
 
 class Adjoint:
-    """Reverse-mode driver of a ``Sim`` (``dg2_adj``): gauge depths after each
+    """Reverse-mode runner of a ``Sim`` (``dg2_adj``): gauge depths after each
     of ``steps`` fixed-size steps from the Sim's current state, and the
     gradients of a loss on them with respect to the per-cell Manning field and
     the samples of the control side's hydrograph.  The Sim must outlive it."""
