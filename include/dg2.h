@@ -396,8 +396,10 @@ dg2_status dg2_batch_time_steps(dg2_batch *b, int32_t nsteps, double *ms_per_ste
  * treatment (which passes no derivative through its decisions).  Where a
  * min/max has equal arguments each receives half; the celerity sqrt(g h) has
  * derivative 0 at h = 0.  Checkpoints of the state are kept every
- * `checkpoint_every` steps and each segment is recomputed once during the
- * backward run.
+ * `checkpoint_every` steps; the forward run also keeps every step of its last
+ * segment, and the backward run recomputes each other segment once from its
+ * checkpoint (with checkpoint_every >= steps nothing is recomputed: the whole
+ * trajectory is kept).  Gradients do not depend on the interval.
  * ------------------------------------------------------------------------ */
 typedef struct dg2_adj dg2_adj;
 

@@ -9,8 +9,12 @@
 // Backward: segments are taken from the last to the first.  A segment is
 // recomputed from its checkpoint with the same production kernels, which
 // now also keep every step's state U^n, stage-1 result U1^n, the wet/dry
-// decisions of both stages and the step record.  The steps of the segment
-// are then reversed, each with two gather kernels (one thread per cell):
+// decisions of both stages and the step record.  The forward run already
+// keeps these for its last segment, so that one is not recomputed (with a
+// checkpoint interval of at least the step count nothing is: the whole
+// trajectory stays in HBM, about 2 states per step).  The steps of the
+// segment are then reversed, each with two gather kernels (one thread per
+// cell):
 //
 //   stage 2:  U^{n+1} = fix(0.5 (W + U1 + dt L(U1)))
 //             lam_U1 = 0.5 mu2 + 0.5 dt (dL/dU1)^T mu2,  mu2 = mask2(lam)
@@ -207,6 +211,7 @@ struct dg2_adj {
   double *U1seg = nullptr;    // K stage-1 results
   unsigned char *mseg = nullptr;  // 2 K wet/dry code planes
   Ctrl *ctrlseg = nullptr;    // K step records
+  int held = -1;              // the segment whose steps the segment buffers hold (-1: none)
   double *lam = nullptr, *lamU1 = nullptr, *Wbuf = nullptr, *gn = nullptr;
   double *lamq = nullptr;     // steps x 2 x ctl_len
   double *seed = nullptr;     // steps x ng
@@ -464,6 +469,15 @@ dg2_status dg2_adj_forward(dg2_adj *a, const double *n_cell, const double *Q, do
   const PlanArgs pa = fwd_plan(a, true);
   ACHK(a, launch_plan(a->actrl, pa, kPlanOnly, std::numeric_limits<double>::infinity(), 1, st), "plan");
   const Scen<double> s = fwd_scen(a, a->Useg, a->U1seg, a->Useg, nullptr, true);
+  // the last segment's steps go to the segment buffers, as the backward
+  // run's recompute would put them there, with the step records
+  const int last0 = (a->nseg - 1) * a->K;
+  PlanArgs pl = pa;
+  pl.hist = a->ctrlseg;
+  pl.hist_len = a->K;
+  pl.hist_base = a->step0 + last0;
+  a->held = -1;
+  const size_t P = (size_t)c->P;
   ACHK(a, hipEventRecord(ev[0], st), "event");
   for (int n = 0; n < a->steps; ++n) {
     if (n % a->K == 0) {
@@ -471,7 +485,18 @@ dg2_status dg2_adj_forward(dg2_adj *a, const double *n_cell, const double *Q, do
       ACHK(a, hipMemcpyAsync(state(a->ckpt, a, k), a->Useg, a->sb, hipMemcpyDeviceToDevice, st), "checkpoint");
       ACHK(a, hipMemcpyAsync(a->ckctrl + k, a->actrl, sizeof(Ctrl), hipMemcpyDeviceToDevice, st), "checkpoint");
     }
-    ACHK(a, queue_fwd_step(a, s, s, pa), "forward step");
+    if (n < last0) {
+      ACHK(a, queue_fwd_step(a, s, s, pa), "forward step");
+      continue;
+    }
+    const int m = n - last0;
+    if (m == 0)
+      ACHK(a, hipMemcpyAsync(a->ctrlseg, a->actrl, sizeof(Ctrl), hipMemcpyDeviceToDevice, st), "segment");
+    const Scen<double> s1 = fwd_scen(a, state(a->Useg, a, m), state(a->U1seg, a, m), nullptr,
+                                     a->mseg + (size_t)(2 * m) * P, true);
+    const Scen<double> s2 = fwd_scen(a, state(a->Useg, a, m), state(a->U1seg, a, m),
+                                     state(a->Useg, a, m + 1), a->mseg + (size_t)(2 * m + 1) * P, true);
+    ACHK(a, queue_fwd_step(a, s1, s2, pl), "forward step");
   }
   ACHK(a, hipEventRecord(ev[1], st), "event");
   ACHK(a, hipEventSynchronize(ev[1]), "forward");
@@ -491,6 +516,7 @@ dg2_status dg2_adj_forward(dg2_adj *a, const double *n_cell, const double *Q, do
     for (int n = 0; n < a->steps; ++n)
       for (int k = 0; k < ng; ++k) gauge_h[(size_t)n * ng + k] = rec[((size_t)n * ng + k) * 4];
   }
+  a->held = a->nseg - 1;
   a->forward_done = true;
   return DG2_OK;
 }
@@ -522,17 +548,25 @@ dg2_status dg2_adj_backward(dg2_adj *a, const double *dL_dh, double *grad_n, dou
   pa.hist_len = K;
   for (int sg = a->nseg - 1; sg >= 0; --sg) {
     const int n0 = sg * K, len = (N - n0) < K ? (N - n0) : K;
-    // recompute the segment, keeping every step
-    ACHK(a, hipMemcpyAsync(a->Useg, state(a->ckpt, a, sg), a->sb, hipMemcpyDeviceToDevice, st), "restore");
-    ACHK(a, hipMemcpyAsync(a->actrl, a->ckctrl + sg, sizeof(Ctrl), hipMemcpyDeviceToDevice, st), "restore");
-    ACHK(a, hipMemcpyAsync(a->ctrlseg, a->ckctrl + sg, sizeof(Ctrl), hipMemcpyDeviceToDevice, st), "restore");
-    pa.hist_base = a->step0 + n0;
-    for (int m = 0; m < len; ++m) {
-      const Scen<double> s1 = fwd_scen(a, state(a->Useg, a, m), state(a->U1seg, a, m), nullptr,
-                                       a->mseg + (size_t)(2 * m) * P, false);
-      const Scen<double> s2 = fwd_scen(a, state(a->Useg, a, m), state(a->U1seg, a, m),
-                                       state(a->Useg, a, m + 1), a->mseg + (size_t)(2 * m + 1) * P, false);
-      ACHK(a, queue_fwd_step(a, s1, s2, pa), "recompute step");
+    // recompute the segment, keeping every step, unless the buffers hold it
+    if (a->held != sg) {
+      a->held = -1;
+      ACHK(a, hipMemcpyAsync(a->Useg, state(a->ckpt, a, sg), a->sb, hipMemcpyDeviceToDevice, st),
+           "restore");
+      ACHK(a, hipMemcpyAsync(a->actrl, a->ckctrl + sg, sizeof(Ctrl), hipMemcpyDeviceToDevice, st),
+           "restore");
+      ACHK(a, hipMemcpyAsync(a->ctrlseg, a->ckctrl + sg, sizeof(Ctrl), hipMemcpyDeviceToDevice, st),
+           "restore");
+      pa.hist_base = a->step0 + n0;
+      for (int m = 0; m < len; ++m) {
+        const Scen<double> s1 = fwd_scen(a, state(a->Useg, a, m), state(a->U1seg, a, m), nullptr,
+                                         a->mseg + (size_t)(2 * m) * P, false);
+        const Scen<double> s2 = fwd_scen(a, state(a->Useg, a, m), state(a->U1seg, a, m),
+                                         state(a->Useg, a, m + 1), a->mseg + (size_t)(2 * m + 1) * P,
+                                         false);
+        ACHK(a, queue_fwd_step(a, s1, s2, pa), "recompute step");
+      }
+      a->held = sg;
     }
     // reverse the segment's steps
     for (int m = len - 1; m >= 0; --m) {

@@ -94,12 +94,19 @@ def test_adjoint_matches_oracle_reverse_mode(n, steps, every):
 
 
 def test_checkpoint_interval_does_not_change_the_gradient():
+    """Bitwise the same gradients whatever the checkpoint interval: the
+    forward run keeps its last segment (with every >= steps the whole
+    trajectory, nothing recomputed), the backward run recomputes the others;
+    a second backward run on the same forward run recomputes the last
+    segment too (7: ragged segments 7, 7, 6)."""
     _say("checkpoint interval invariance")
     c, man, Q, target = _case(66, 20, nsamples=5)
     res = []
-    for every in (1, 7, 20):
+    for every in (1, 7, 20, 30):
         s, a, h, J, gn, gq = _gpu_grads(c, man, Q, target, every)
         res.append((h, gn, gq))
+        gn2, gq2 = a.backward(2.0 * (h - target))
+        assert np.array_equal(gn2, gn) and np.array_equal(gq2, gq), every
         a.close()
         s.close()
     for h, gn, gq in res[1:]:
