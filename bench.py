@@ -348,7 +348,7 @@ def main():
     ms1, ms2, ms_step_ev = sim.time_kernels(args.steps)
     torch.cuda.synchronize()
     # the fused kernel ran iff there was no separate stage-2 launch (it
-    # applies to FP32 DG2-NL only; other workloads use the stage kernels)
+    # applies to DG2-NL; DG2-LL workloads use the stage kernels)
     fused = ms2 == 0.0
 
     cells = sc.nx * sc.ny

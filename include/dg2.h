@@ -269,8 +269,8 @@ dg2_status dg2_set_partly_wet_flat(dg2_ctx *ctx, int32_t on);
 /* How dg2_step runs the two RK stages of Sec. 2.1.2.  fused = 1 (default):
  * one kernel per step that computes stage 1 a row ahead of stage 2 and keeps
  * the stage-1 result in registers, so a step reads and writes the state once;
- * it applies to DG2-NL in FP32 with the state in library memory (otherwise
- * the per-stage kernels run).  fused = 0: one kernel per stage, with the stage-1
+ * it applies to DG2-NL (FP32 and FP64) with the state in library memory
+ * (otherwise the per-stage kernels run).  fused = 0: one kernel per stage, with the stage-1
  * result in a device buffer.  Results are bitwise the same.  DG2_EINVAL for
  * other values. */
 dg2_status dg2_set_step_kernel(dg2_ctx *ctx, int32_t fused);

@@ -140,9 +140,10 @@ hipError_t queue_plan(dg2_ctx *c, int mode, double t_end = 0.0, int set_tend = 0
 }
 
 // Both stages in one kernel into the second buffer, which becomes the state.
-hipError_t queue_fused(dg2_ctx *c) {
-  Scen<float> s = scen<float>(c);
-  s.Uout = (float *)c->U1;
+template <typename real>
+hipError_t queue_fused_as(dg2_ctx *c) {
+  Scen<real> s = scen<real>(c);
+  s.Uout = (real *)c->U1;
   hipError_t e;
   if (c->stage_check > 0) {
     // trials of the whole step against the staging block; once one is
@@ -151,15 +152,16 @@ hipError_t queue_fused(dg2_ctx *c) {
     s.ctrl = c->ctrl2;
     e = launch_fused_check(c->ctrl, c->ctrl2, pa, 1, 0, c->stream);
     for (int k = 0; k <= c->stage_check && e == hipSuccess; ++k) {
-      e = launch_fused<float>(s, consts(c), fused_launch_of(c), c->stream, true);
+      e = launch_fused<real>(s, consts(c), fused_launch_of(c), c->stream, true);
       if (e == hipSuccess) e = launch_fused_check(c->ctrl, c->ctrl2, pa, 0, k == c->stage_check, c->stream);
     }
   } else {
-    e = launch_fused<float>(s, consts(c), fused_launch_of(c), c->stream);
+    e = launch_fused<real>(s, consts(c), fused_launch_of(c), c->stream);
   }
   if (e == hipSuccess) std::swap(c->U, c->U1);
   return e;
 }
+hipError_t queue_fused(dg2_ctx *c) { return c->f32 ? queue_fused_as<float>(c) : queue_fused_as<double>(c); }
 
 dg2_status queue_step(dg2_ctx *c, hipEvent_t *ev = nullptr) {
   if (fused_active(c)) {
@@ -1091,6 +1093,7 @@ hipError_t batch_plan(dg2_batch *b, int mode, double t_end = 0.0, int set_tend =
 }
 
 dg2_status batch_queue_step(dg2_batch *b) {
+  if (b->fused && !b->f32) return bfail(b, DG2_ESTATE, "the batched fused step kernel is FP32 only");
   if (b->fused) {
     const Scen<float> *tab = (const Scen<float> *)b->d_scens + (size_t)b->par * b->m.size();
     BCHK(b, launch_batch_fused(tab, b->d_items, b->nitems, b->consts, b->R, b->wpb, b->blocksF,
@@ -1172,7 +1175,9 @@ dg2_status batch_setup(dg2_batch *b) {
   for (auto *c : b->m)
     if (c->stage_check > 0)
       return bfail(b, DG2_EINVAL, "the stage-1 Courant check is not available in batches");
-  b->fused = true;
+  // the batched fused step kernel is FP32 (FP64 batches run the per-stage
+  // batch kernels, whatever their members run alone)
+  b->fused = b->f32;
   for (auto *c : b->m) b->fused = b->fused && fused_active(c);
   if (b->fused && b->graph_steps > 1 && (b->graph_steps & 1)) b->graph_steps += 1;
   dg2_status st = b->f32 ? upload_scens<float>(b) : upload_scens<double>(b);

@@ -147,11 +147,11 @@ inline Consts consts(const dg2_ctx *c) {
   return k;
 }
 
-// Both RK stages in one kernel: DG2-NL in FP32 with the state in library
-// memory.  (In FP64 the fused kernel needs more registers than three
-// wavefronts per SIMD allow and runs slower than the stage kernels.)
+// Both RK stages in one kernel: DG2-NL with the state in library memory.
+// FP32 runs three wavefronts per SIMD (168 VGPRs); FP64 one, whose 256 VGPRs
+// and the accumulation registers hold the march without scratch.
 inline bool fused_active(const dg2_ctx *c) {
-  return c->fused_user && c->f32 && c->cfg.variant == DG2_NL &&
+  return c->fused_user && c->cfg.variant == DG2_NL &&
          (c->U == c->U_own || c->U == c->U1_own);
 }
 

@@ -59,7 +59,7 @@ template <typename real>
 hipError_t launch_stage(int stage, int variant, const Scen<real> &s, const Consts &c,
                         const Launch &L, hipStream_t st);
 
-// Both RK stages of a DG2-NL step in one launch (FP32); writes s.Uout,
+// Both RK stages of a DG2-NL step in one launch; writes s.Uout,
 // which must not alias s.U.
 template <typename real>
 hipError_t launch_fused(const Scen<real> &s, const Consts &c, const Launch &L, hipStream_t st,

@@ -19,7 +19,7 @@
 // per wavefront; a single-thread plan kernel then turns the minimum into the
 // next step size on the device, so queued steps never wait for the host.
 //
-// For FP32 DG2-NL the fused step kernel further down runs both stages in one
+// For DG2-NL the fused step kernel further down runs both stages in one
 // pass, stage 1 a row ahead of stage 2 with its result in registers, and
 // writes the new state to a second buffer.
 //
@@ -1020,7 +1020,7 @@ __device__ __forceinline__ void fused_tile(const Scen<real> &s, const Consts &c,
 }
 
 template <typename real, int FLUX, bool CHECK>
-__global__ void __launch_bounds__(256, 3) k_step_nl(Scen<real> s, Consts c, Launch L) {
+__global__ void __launch_bounds__(256, sizeof(real) == 8 ? 1 : 3) k_step_nl(Scen<real> s, Consts c, Launch L) {
   int item;
   if (!stage_item<2>(L, item)) return;
   const int strip = item % L.nstrips, seg = item / L.nstrips;
@@ -1939,6 +1939,8 @@ template hipError_t launch_stage<double>(int, int, const Scen<double> &, const C
 template hipError_t launch_stage<float>(int, int, const Scen<float> &, const Consts &,
                                         const Launch &, hipStream_t);
 template hipError_t launch_fused<float>(const Scen<float> &, const Consts &, const Launch &,
+                                        hipStream_t, bool);
+template hipError_t launch_fused<double>(const Scen<double> &, const Consts &, const Launch &,
                                         hipStream_t, bool);
 template hipError_t launch_cfl<double>(const Scen<double> &, const Consts &, hipStream_t, const Ctrl *,
                                        unsigned long long *);

@@ -1,12 +1,11 @@
 """The fused DG2-NL step kernel (both RK stages of Sec. 2.1.2 in one pass,
-the stage-1 result kept in registers; FP32) against the per-stage kernels,
+the stage-1 result kept in registers; FP32 and FP64) against the per-stage kernels,
 through the C ABI: states, times, step sizes, gauge series and diagnostics
 are bitwise equal, on ragged grids (strip and segment edges, single rows and
 columns), with every boundary kind, inflows, rain and per-cell Manning, HLL
 and Roe, at every launch shape; the state may be bound to caller memory or
-shared with a batch.  FP64 contexts run the per-stage kernels.  The FP32
-oracle comparisons of the other files run the fused kernel too, since it is
-the default."""
+shared with a batch.  The oracle comparisons of the other files (FP64 and
+FP32 DG2-NL) run the fused kernel too, since it is the default."""
 import numpy as np
 import pytest
 import torch
@@ -65,7 +64,7 @@ SIZES = [(70, 45), (1, 5), (6, 1), (60, 7), (61, 3), (120, 9), (121, 130), (59, 
 
 
 @pytest.mark.parametrize("nx,ny", SIZES)
-@pytest.mark.parametrize("prec,flux", [("fp32", "HLL"), ("fp32", "ROE")])
+@pytest.mark.parametrize("prec,flux", [("fp32", "HLL"), ("fp32", "ROE"), ("fp64", "HLL"), ("fp64", "ROE")])
 def test_fused_step_equals_stage_kernels(nx, ny, prec, flux):
     _say("fused vs per-stage", nx, ny, prec, flux)
     a, b = _pair(_random_sim(nx, ny, prec, flux, seed=nx * 100 + ny))
@@ -75,9 +74,10 @@ def test_fused_step_equals_stage_kernels(nx, ny, prec, flux):
         _same(a, b, "%dx%d %s %s after %d more steps" % (nx, ny, prec, flux, k))
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("rows,wpb", [(1, 1), (2, 4), (3, 2), (5, 4), (8, 1), (13, 4), (200, 4)])
-def test_fused_step_launch_shapes(rows, wpb):
-    make = _random_sim(125, 77, "fp32", "HLL", seed=3)
+def test_fused_step_launch_shapes(rows, wpb, prec):
+    make = _random_sim(125, 77, prec, "HLL", seed=3)
     a, b = _pair(make)
     a.set_launch(rows, wpb)
     a.step(3)
@@ -85,14 +85,15 @@ def test_fused_step_launch_shapes(rows, wpb):
     _same(a, b, "rows %d wpb %d" % (rows, wpb))
 
 
-def test_fused_dam_break_and_floodplain_runs():
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_fused_dam_break_and_floodplain_runs(prec):
     sc = WL.dambreak_bump()
-    a, b = _pair(lambda: dg2.sim_from_scenario(sc, precision="fp32"))
+    a, b = _pair(lambda: dg2.sim_from_scenario(sc, precision=prec))
     a.step(sc.steps)
     b.step(sc.steps)
     _same(a, b, "dam break 500 steps")
     sc = WL.floodplain()
-    a, b = _pair(lambda: dg2.sim_from_scenario(sc, precision="fp32"))
+    a, b = _pair(lambda: dg2.sim_from_scenario(sc, precision=prec))
     a.step(300)
     b.step(300)
     _same(a, b, "floodplain 300 steps")
@@ -168,8 +169,15 @@ def test_batch_after_a_member_was_stepped_alone():
     batch.close()
 
 
-def test_fp64_runs_the_stage_kernels():
+def test_fp64_runs_the_fused_kernel_and_ll_the_stage_kernels():
     s = _random_sim(40, 30, "fp64", "HLL", seed=9)()
+    ms1, ms2, _ = s.time_kernels(2)
+    assert ms1 > 0 and ms2 == 0
+    s.set_step_kernel(False)
+    ms1, ms2, _ = s.time_kernels(2)
+    assert ms1 > 0 and ms2 > 0
+    sc = WL.dambreak_bump(variant="LL")
+    s = dg2.sim_from_scenario(sc, precision="fp64")
     ms1, ms2, _ = s.time_kernels(2)
     assert ms1 > 0 and ms2 > 0
 

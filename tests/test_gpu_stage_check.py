@@ -88,15 +88,16 @@ def test_checked_fp32():
     assert np.abs(st[0] - r64[0]).max() < 1e-2
 
 
-@pytest.mark.parametrize("flux,nx,ny,row0", [("HLL", 40, 40, 236), ("ROE", 40, 40, 236),
-                                             ("HLL", 200, 100, 200)])
-def test_checked_fused_step_kernel_matches_per_stage_kernels(flux, nx, ny, row0):
-    """With the fused step kernel (the FP32 default) the check tries the
+@pytest.mark.parametrize("flux,nx,ny,row0,prec", [("HLL", 40, 40, 236, "fp32"), ("ROE", 40, 40, 236, "fp32"),
+                                                  ("HLL", 200, 100, 200, "fp32"),
+                                                  ("HLL", 200, 100, 200, "fp64")])
+def test_checked_fused_step_kernel_matches_per_stage_kernels(flux, nx, ny, row0, prec):
+    """With the fused step kernel (the default) the check tries the
     whole step; each trial computes stage 1 as the matching repeat of the
     per-stage check does, so both paths take the same step sizes and give
     the same states, bit for bit.  The 200 x 100 corner has interior tiles
     (halo inside the grid) beside the inflow mouth."""
-    sc = WL.floodplain_mouth(nx=nx, ny=ny, row0=row0, stage_check=3, precision="fp32")
+    sc = WL.floodplain_mouth(nx=nx, ny=ny, row0=row0, stage_check=3, precision=prec)
     sc.flux = flux
     a = dg2.sim_from_scenario(sc)
     b = dg2.sim_from_scenario(sc)
@@ -115,8 +116,8 @@ def test_checked_fused_step_kernel_matches_per_stage_kernels(flux, nx, ny, row0)
         assert ta == tb and da == db, (n, ta, tb, da, db)
         assert np.array_equal(sa, sb), (n, np.abs(sa - sb).max())
         hmin = min(hmin, float(sa[0].min()))
-    _say("stage check, fused vs per-stage kernels, FP32 %s, %d x %d, 200 steps: t %.9f, min h0 %.2e"
-         % (flux, nx, ny, ta, hmin))
+    _say("stage check, fused vs per-stage kernels, %s %s, %d x %d, 200 steps: t %.9f, min h0 %.2e"
+         % (prec, flux, nx, ny, ta, hmin))
     assert hmin >= -1e-6
     # run-to with trials: the target is still met exactly, in the same steps
     T = float(np.ceil(ta)) + 5.0
