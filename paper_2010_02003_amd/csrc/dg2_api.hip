@@ -1093,12 +1093,15 @@ hipError_t batch_plan(dg2_batch *b, int mode, double t_end = 0.0, int set_tend =
 }
 
 dg2_status batch_queue_step(dg2_batch *b) {
-  if (b->fused && !b->f32) return bfail(b, DG2_ESTATE, "the batched fused step kernel is FP32 only");
   if (b->fused) {
-    const Scen<float> *tab = (const Scen<float> *)b->d_scens + (size_t)b->par * b->m.size();
-    BCHK(b, launch_batch_fused(tab, b->d_items, b->nitems, b->consts, b->R, b->wpb, b->blocksF,
-                               b->stream),
-         "batch step");
+    // the scenario table holds Scen<real> of the batch's precision
+    const size_t at = (size_t)b->par * b->m.size();
+    const hipError_t e =
+        b->f32 ? launch_batch_fused<float>((const Scen<float> *)b->d_scens + at, b->d_items, b->nitems,
+                                           b->consts, b->R, b->wpb, b->blocksF, b->stream)
+               : launch_batch_fused<double>((const Scen<double> *)b->d_scens + at, b->d_items, b->nitems,
+                                            b->consts, b->R, b->wpb, b->blocksF, b->stream);
+    BCHK(b, e, "batch step");
     BCHK(b, batch_plan(b, kPlanFinishStep), "batch plan");
     b->par ^= 1;
     for (size_t k = 0; k < b->m.size(); ++k) {
@@ -1175,9 +1178,7 @@ dg2_status batch_setup(dg2_batch *b) {
   for (auto *c : b->m)
     if (c->stage_check > 0)
       return bfail(b, DG2_EINVAL, "the stage-1 Courant check is not available in batches");
-  // the batched fused step kernel is FP32 (FP64 batches run the per-stage
-  // batch kernels, whatever their members run alone)
-  b->fused = b->f32;
+  b->fused = true;
   for (auto *c : b->m) b->fused = b->fused && fused_active(c);
   if (b->fused && b->graph_steps > 1 && (b->graph_steps & 1)) b->graph_steps += 1;
   dg2_status st = b->f32 ? upload_scens<float>(b) : upload_scens<double>(b);
@@ -1185,7 +1186,7 @@ dg2_status batch_setup(dg2_batch *b) {
   if ((st = build_items(b)) != DG2_OK) return st;
   const int fx = b->consts.flux;
   if (b->fused) {
-    b->blocksF = batch_fused_blocks(fx, b->wpb);
+    b->blocksF = b->f32 ? batch_fused_blocks<float>(fx, b->wpb) : batch_fused_blocks<double>(fx, b->wpb);
     const int need = (b->nitems + b->wpb - 1) / b->wpb;
     if (b->blocksF > need) b->blocksF = need;
     if (b->blocksF < 1) b->blocksF = 1;

@@ -110,10 +110,12 @@ hipError_t launch_batch_status(Ctrl *const *ctrls, int n, unsigned *out, hipStre
 template <typename real>
 int batch_blocks(int stage, int variant, int flux, int wpb);
 
-// Fused step of a batch of FP32 DG2-NL scenarios (one launch per step); each
-// table entry's Uout must not alias its U.
-hipError_t launch_batch_fused(const Scen<float> *scens, const void *items, int nitems, const Consts &c,
+// Fused step of a batch of DG2-NL scenarios of one precision (one launch
+// per step); each table entry's Uout must not alias its U.
+template <typename real>
+hipError_t launch_batch_fused(const Scen<real> *scens, const void *items, int nitems, const Consts &c,
                               int R, int wpb, int blocks, hipStream_t st);
+template <typename real>
 int batch_fused_blocks(int flux, int wpb);
 
 enum PlanMode { kPlanOnly = 0, kPlanFromMin = 1, kPlanFinishStep = 2 };

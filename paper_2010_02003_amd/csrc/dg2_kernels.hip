@@ -1326,12 +1326,12 @@ __global__ void __launch_bounds__(256, 2) k_batch_stage(const Scen<real> *__rest
   }
 }
 
-// Fused step (both RK stages, FP32 DG2-NL) for a batch: the same
+// Fused step (both RK stages, DG2-NL) for a batch: the same
 // persistent stride over the work items, each running the fused march on its
 // scenario; the scenario table gives each member's current state (U) and
 // the buffer its next state goes to (Uout).
 template <typename real, int FLUX>
-__global__ void __launch_bounds__(256, 3) k_batch_step(const Scen<real> *__restrict__ scens,
+__global__ void __launch_bounds__(256, sizeof(real) == 8 ? 1 : 3) k_batch_step(const Scen<real> *__restrict__ scens,
                                                     const Item *__restrict__ items, int nitems,
                                                     Consts c, int R, int wpb) {
   const int lane = threadIdx.x & 63;
@@ -1899,6 +1899,7 @@ int batch_blocks(int stage, int variant, int flux, int wpb) {
 template int batch_blocks<double>(int, int, int, int);
 template int batch_blocks<float>(int, int, int, int);
 
+template <typename real>
 int batch_fused_blocks(int flux, int wpb) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1024;
@@ -1906,22 +1907,30 @@ int batch_fused_blocks(int flux, int wpb) {
   const int threads = 64 * wpb;
   const hipError_t e =
       flux == kFluxRoe
-          ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_step<float, kFluxRoe>, threads, 0)
-          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_step<float, kFluxHLL>, threads, 0);
+          ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_step<real, kFluxRoe>, threads, 0)
+          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_step<real, kFluxHLL>, threads, 0);
   if (e != hipSuccess || per < 1) per = 1;
   return per * cus;
 }
 
-hipError_t launch_batch_fused(const Scen<float> *scens, const void *items, int nitems, const Consts &c,
+template <typename real>
+hipError_t launch_batch_fused(const Scen<real> *scens, const void *items, int nitems, const Consts &c,
                               int R, int wpb, int blocks, hipStream_t st) {
   const Item *it = (const Item *)items;
   const dim3 block(64 * wpb), grid(blocks);
   if (c.flux == kFluxRoe)
-    hipLaunchKernelGGL((k_batch_step<float, kFluxRoe>), grid, block, 0, st, scens, it, nitems, c, R, wpb);
+    hipLaunchKernelGGL((k_batch_step<real, kFluxRoe>), grid, block, 0, st, scens, it, nitems, c, R, wpb);
   else
-    hipLaunchKernelGGL((k_batch_step<float, kFluxHLL>), grid, block, 0, st, scens, it, nitems, c, R, wpb);
+    hipLaunchKernelGGL((k_batch_step<real, kFluxHLL>), grid, block, 0, st, scens, it, nitems, c, R, wpb);
   return hipGetLastError();
 }
+
+template int batch_fused_blocks<float>(int, int);
+template int batch_fused_blocks<double>(int, int);
+template hipError_t launch_batch_fused<float>(const Scen<float> *, const void *, int, const Consts &, int,
+                                              int, int, hipStream_t);
+template hipError_t launch_batch_fused<double>(const Scen<double> *, const void *, int, const Consts &,
+                                               int, int, int, hipStream_t);
 
 hipError_t launch_plan_batch(Ctrl *const *ctrls, const PlanArgs *pa, int n, int mode, double t_end,
                              int set_tend, hipStream_t st) {

@@ -35,7 +35,8 @@ def _members(k, precision="fp32", variant="NL", shrink=4):
 
 
 @pytest.mark.parametrize("precision,variant,graph", [("fp32", "NL", 16), ("fp32", "NL", 1),
-                                                     ("fp64", "NL", 8), ("fp32", "LL", 4)])
+                                                     ("fp64", "NL", 8), ("fp64", "NL", 1),
+                                                     ("fp32", "LL", 4)])
 def test_batch_equals_plain_runs(precision, variant, graph):
     scs = _members(7, precision, variant)
     _say("batch of", len(scs), precision, variant, "graph steps", graph, [(s.nx, s.ny) for s in scs])
@@ -74,8 +75,9 @@ def test_batch_run_to_and_per_scenario_dt():
     assert len(set(dts)) > 1  # scenarios really took different step sizes
 
 
-def test_batch_autotune_keeps_results():
-    scs = _members(6, "fp32", "NL")
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_autotune_keeps_results(precision):
+    scs = _members(6, precision, "NL")
     sims = [dg2.sim_from_scenario(sc) for sc in scs]
     b = dg2.Batch(sims)
     b.step(10)

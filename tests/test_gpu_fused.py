@@ -152,10 +152,11 @@ def test_fused_with_bound_state_and_unbind():
     _same(a, b, "unbound again")
 
 
-def test_batch_after_a_member_was_stepped_alone():
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_after_a_member_was_stepped_alone(prec):
     scs = [WL.ensemble(3)[k] for k in range(3)]
-    sims = [dg2.sim_from_scenario(sc) for sc in scs]
-    plain = [dg2.sim_from_scenario(sc) for sc in scs]
+    sims = [dg2.sim_from_scenario(sc, precision=prec) for sc in scs]
+    plain = [dg2.sim_from_scenario(sc, precision=prec) for sc in scs]
     batch = dg2.Batch(sims)
     sims[1].step(1)  # fused: member 1's state moves to its other buffer
     plain[1].step(1)
